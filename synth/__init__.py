@@ -1,0 +1,256 @@
+"""Seeded synthetic workloads for the MSV/SSV filters.
+
+This module only draws random inputs: per-node emission probabilities of a
+profile, sequence lengths, residue codes, implanted high-scoring segments and
+request arrival times.  It holds none of the filters' arithmetic (no log-odds,
+no quantization, no dynamic programming), so both the CPU oracle and the GPU
+library can be fed from it without sharing any of the method.
+
+The paper measures on Pfam 27.0 query models (lengths 7..2405) against the
+env_nr and est_human protein databases (Sec. 4, Table 2).  None of those data
+are available here; the workloads below stand in for them with the same kind
+of shapes: peaked per-node emission distributions, lognormal protein lengths
+with a mean between the two databases' means (197 and 511), and residues drawn
+from a standard background composition.
+
+Residue codes: 0..19 are the amino acids in the order ``ALPHABET``; codes
+20..31 are non-scoring (invalid) residues.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+ALPHABET = "ACDEFGHIKLMNPQRSTVWY"
+K = 20          # scoring alphabet size
+KP = 32         # full code space (20..31 are non-scoring)
+
+# Amino-acid background composition: the BLOSUM62 background frequencies
+# (Henikoff & Henikoff, PNAS 1992), three decimals, in ALPHABET order.  They
+# sum to exactly 1.000.
+BG = np.array([0.074, 0.025, 0.054, 0.054, 0.047, 0.074, 0.026, 0.068, 0.058,
+               0.099, 0.025, 0.045, 0.039, 0.034, 0.052, 0.057, 0.051, 0.073,
+               0.013, 0.032], dtype=np.float64)
+BG = BG / BG.sum()
+
+# Lognormal protein lengths: mean ~350, sd ~300, clipped to [20, 35000].
+LOGNORMAL_MU = 5.5825
+LOGNORMAL_SIGMA = 0.7422
+LEN_MIN, LEN_MAX = 20, 35000
+
+# Order of the spawned child streams of one seed.
+_STREAMS = ("profile", "lengths", "residues", "implants", "arrivals")
+
+
+def streams(seed: int) -> dict:
+    """Named, independent generators spawned from one seed."""
+    kids = np.random.SeedSequence(seed).spawn(len(_STREAMS))
+    return {name: np.random.default_rng(s) for name, s in zip(_STREAMS, kids)}
+
+
+def sample_emissions(rng: np.random.Generator, M: int, conc: float = 0.5) -> np.ndarray:
+    """Per-node match emission probabilities, float64 [M, 20].
+
+    Each node is Dirichlet(conc * BG).  The concentrations are small (about
+    0.006..0.05), so Gamma draws are taken in log space
+    (Gamma(a) = Gamma(a+1) * U**(1/a)) to avoid underflow before normalising.
+    Entries can still be exactly 0 after exponentiation; that is a legal
+    profile (such a residue can never be emitted by that node).
+    """
+    a = conc * BG
+    g1 = rng.gamma(a + 1.0, size=(M, K))
+    u = rng.random(size=(M, K))
+    u = np.maximum(u, np.finfo(np.float64).tiny)
+    logg = np.log(g1) + np.log(u) / a
+    logg -= logg.max(axis=1, keepdims=True)
+    e = np.exp(logg)
+    e /= e.sum(axis=1, keepdims=True)
+    return e
+
+
+def sample_lengths_uniform(rng, n: int, lo: int, hi: int) -> np.ndarray:
+    return rng.integers(lo, hi + 1, size=n, dtype=np.int64)
+
+
+def sample_lengths_lognormal(rng, n: int) -> np.ndarray:
+    L = np.rint(rng.lognormal(LOGNORMAL_MU, LOGNORMAL_SIGMA, size=n))
+    return np.clip(L, LEN_MIN, LEN_MAX).astype(np.int64)
+
+
+def sample_residues(rng, lengths: np.ndarray, chunk: int = 1 << 24):
+    """i.i.d. residues from BG.  Returns (codes uint8 [sum L], offsets int64 [n+1])."""
+    lengths = np.asarray(lengths, dtype=np.int64)
+    offsets = np.zeros(len(lengths) + 1, dtype=np.int64)
+    np.cumsum(lengths, out=offsets[1:])
+    total = int(offsets[-1])
+    res = np.empty(total, dtype=np.uint8)
+    cdf = np.cumsum(BG)
+    cdf[-1] = 1.0
+    for s in range(0, total, chunk):
+        e = min(total, s + chunk)
+        res[s:e] = np.searchsorted(cdf, rng.random(e - s), side="right").astype(np.uint8)
+    np.minimum(res, K - 1, out=res)
+    return res, offsets
+
+
+def implant(rng, res: np.ndarray, offsets: np.ndarray, emis_list, frac: float = 0.01,
+            which=None):
+    """Overwrite a segment of floor(frac*n) sequences with residues emitted by a profile.
+
+    For a chosen sequence of length L and profile of length M: segment length
+    l ~ U{ceil(min(M,L)/2) .. min(M,L)}, start node k0 ~ U{0 .. M-l},
+    start position p ~ U{0 .. L-l}; residue t is drawn from node k0+t.
+    ``emis_list`` is a list of emission arrays; each implant picks one
+    uniformly (or ``which[i]`` if given).  Returns the implanted sequence ids.
+    """
+    n = len(offsets) - 1
+    cnt = int(np.floor(frac * n))
+    ids = np.sort(rng.choice(n, size=cnt, replace=False)) if cnt else np.zeros(0, np.int64)
+    cdfs = [np.cumsum(e, axis=1) for e in emis_list]
+    for t, sid in enumerate(ids):
+        pi = int(which[t]) if which is not None else int(rng.integers(len(emis_list)))
+        cdf = cdfs[pi]
+        M = cdf.shape[0]
+        L = int(offsets[sid + 1] - offsets[sid])
+        if L == 0:
+            continue
+        mx = min(M, L)
+        lo = (mx + 1) // 2
+        ln = int(rng.integers(lo, mx + 1))
+        k0 = int(rng.integers(0, M - ln + 1))
+        p = int(rng.integers(0, L - ln + 1))
+        u = rng.random(ln)
+        rows = cdf[k0:k0 + ln]
+        codes = (rows < (u[:, None] * rows[:, -1:])).sum(axis=1)
+        res[offsets[sid] + p: offsets[sid] + p + ln] = np.minimum(codes, K - 1).astype(np.uint8)
+    return ids
+
+
+@dataclasses.dataclass
+class Database:
+    res: np.ndarray       # uint8 codes, concatenated
+    offsets: np.ndarray   # int64 [n+1]
+
+    @property
+    def n(self) -> int:
+        return len(self.offsets) - 1
+
+    @property
+    def lengths(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+    @property
+    def residues(self) -> int:
+        return int(self.offsets[-1])
+
+    def seq(self, i: int) -> np.ndarray:
+        return self.res[self.offsets[i]:self.offsets[i + 1]]
+
+    def subset(self, ids) -> "Database":
+        ids = np.asarray(ids, dtype=np.int64)
+        lens = self.lengths[ids]
+        off = np.zeros(len(ids) + 1, dtype=np.int64)
+        np.cumsum(lens, out=off[1:])
+        out = np.empty(int(off[-1]), dtype=np.uint8)
+        for t, i in enumerate(ids):
+            out[off[t]:off[t + 1]] = self.seq(int(i))
+        return Database(out, off)
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    filters: list         # "msv" / "ssv" per query
+    emissions: list       # float64 [M, 20] per query
+    db: Database
+    implanted: np.ndarray
+    seed: int
+
+    @property
+    def Ms(self):
+        return [int(e.shape[0]) for e in self.emissions]
+
+    def cells(self) -> int:
+        return int(sum(self.Ms)) * self.db.residues
+
+
+def plain_msv_m48(seed: int = 1, nseq: int = 2000) -> Workload:
+    """Plain MSV, M=48, lengths U{50..500}, residues i.i.d. from BG."""
+    st = streams(seed)
+    emis = sample_emissions(st["profile"], 48)
+    L = sample_lengths_uniform(st["lengths"], nseq, 50, 500)
+    res, off = sample_residues(st["residues"], L)
+    return Workload("msv_m48_2k", ["msv"], [emis], Database(res, off),
+                    np.zeros(0, np.int64), seed)
+
+
+def lognormal_db(seed: int, nseq: int, implant_emis=None, frac: float = 0.01, st=None):
+    st = st or streams(seed)
+    L = sample_lengths_lognormal(st["lengths"], nseq)
+    res, off = sample_residues(st["residues"], L)
+    ids = np.zeros(0, np.int64)
+    if implant_emis:
+        ids = implant(st["implants"], res, off, implant_emis, frac)
+    return Database(res, off), ids
+
+
+def plain_msv_m400(seed: int = 2, nseq: int = 500_000) -> Workload:
+    """Plain MSV, M=400, lognormal lengths, 1% implants from the query itself."""
+    st = streams(seed)
+    emis = sample_emissions(st["profile"], 400)
+    db, ids = lognormal_db(seed, nseq, [emis], 0.01, st)
+    return Workload("msv_m400_500k", ["msv"], [emis], db, ids, seed)
+
+
+def plain_ssv(seed: int = 3, nseq: int = 500_000, Ms=(100, 400, 1000, 2400),
+              db: Database | None = None, implanted=None) -> Workload:
+    """Plain SSV queries of several lengths against the 500k lognormal database.
+
+    The database is the M=400 MSV workload's (seed 2) unless one is given."""
+    st = streams(seed)
+    emis = [sample_emissions(st["profile"], int(m)) for m in Ms]
+    if db is None:
+        base = plain_msv_m400(nseq=nseq)
+        db, implanted = base.db, base.implanted
+    return Workload("ssv_500k", ["ssv"] * len(Ms), emis, db,
+                    implanted if implanted is not None else np.zeros(0, np.int64), seed)
+
+
+def batched(seed: int = 4, nseq: int = 1_000_000, nq: int = 64, mlo: int = 30,
+            mhi: int = 2400) -> Workload:
+    """64 queries, M ~ U{30..2400}, MSV/SSV alternating, 1M-sequence lognormal DB.
+
+    Implants are drawn from the queries, each implant's profile uniform."""
+    st = streams(seed)
+    Ms = st["profile"].integers(mlo, mhi + 1, size=nq)
+    emis = [sample_emissions(st["profile"], int(m)) for m in Ms]
+    filt = ["msv" if i % 2 == 0 else "ssv" for i in range(nq)]
+    db, ids = lognormal_db(seed, nseq, emis, 0.01, st)
+    return Workload("batched_64q_1m", filt, emis, db, ids, seed)
+
+
+def served_db(seed: int = 5, nseq: int = 2_000_000) -> Database:
+    st = streams(seed)
+    db, _ = lognormal_db(seed, nseq, None, 0.0, st)
+    return db
+
+
+def request_trace(seed: int, nreq: int, qps: float, mlo: int = 30, mhi: int = 2000):
+    """Poisson arrivals.  Returns (arrival times s, M per request, filter per
+    request, emissions per request)."""
+    kids = np.random.SeedSequence([seed, 0x5E4F]).spawn(2)
+    ra = np.random.default_rng(kids[0])
+    rp = np.random.default_rng(kids[1])
+    gaps = ra.exponential(1.0 / qps, size=nreq)
+    t = np.cumsum(gaps) - gaps[0]
+    Ms = rp.integers(mlo, mhi + 1, size=nreq)
+    filt = ["msv" if b else "ssv" for b in (rp.random(nreq) < 0.5)]
+    emis = [sample_emissions(rp, int(m)) for m in Ms]
+    return t, Ms, filt, emis
+
+
+def random_db(rng, nseq: int, lo: int, hi: int) -> Database:
+    """Small helper for tests: uniform lengths in [lo, hi], i.i.d. residues."""
+    L = rng.integers(lo, hi + 1, size=nseq).astype(np.int64)
+    res, off = sample_residues(rng, L)
+    return Database(res, off)

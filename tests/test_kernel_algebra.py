@@ -1,0 +1,109 @@
+"""CPU model of the reformulations the GPU kernels rely on, checked against the oracle.
+
+The kernels do not run the oracle's loop literally.  They rely on four facts,
+each checked here on random inputs in every regime (no hit, J loop, overflow):
+
+I1  a running maximum of the match scores (never reset per row) yields the
+    same scJ, because max and "minus tec, floored at 0" commute;
+I2  before the first overflow row the 255 (MSV) / 127 (SSV) caps never fire,
+    so the kernels can work without the upper clamp and flag overflow once
+    the running maximum reaches the threshold;
+I3  rows of non-scoring residues appended after a target (row padding) change
+    neither the running maximum nor the score;
+I4  scB only changes when the running maximum passes max(base + tec, the value
+    scB was last computed from), so rows can be run in tiles with scB fixed,
+    checked at the tile end, and replayed row by row only when it moved.
+"""
+import numpy as np
+
+import oracle
+from oracle import quant as q
+import synth
+
+
+def model_msv(prof, x, tile=8, pad=4):
+    M, bias = prof["M"], prof["bias"]
+    s = bias - prof["cost"].astype(np.int64)          # score added per cell
+    L = len(x)
+    rows = list(x) + [20] * ((-L) % pad if L else pad)
+    tjbm = q.tjb(L) + prof["tbm"]
+    tec, base = q.tec(), q.BASE
+
+    def xb_of(m):
+        return max(0, max(base, m - tec) - tjbm)
+
+    R = np.zeros(M, np.int64)
+    run = 0                       # running max of cell values (I1)
+    built_from = -(1 << 30)       # running max that scB was computed from
+    xB = xb_of(built_from)
+    flag = False
+    i = 0
+    while i < len(rows):
+        n = min(tile, len(rows) - i)
+        ck_R, ck_run = R.copy(), run
+        for t in range(n):                             # fast rows: scB fixed
+            g = np.concatenate(([0], R[:-1]))
+            R = np.maximum(0, np.maximum(g, xB) + s[rows[i + t]])   # no cap (I2)
+            run = max(run, int(R.max()))
+        moved = run > max(base + tec, built_from) or run >= 255 - bias
+        if moved and not flag:                         # replay exactly (I4)
+            R, run = ck_R, ck_run
+            for t in range(n):
+                g = np.concatenate(([0], R[:-1]))
+                R = np.maximum(0, np.maximum(g, xB) + s[rows[i + t]])
+                run = max(run, int(R.max()))
+                if run >= 255 - bias:
+                    flag = True
+                xB = xb_of(run)
+                built_from = run
+        i += n
+    return (255, 1) if flag else (max(0, run - tec), 0)
+
+
+def model_ssv(prof, x, pad=4):
+    M = prof["M"]
+    sc = prof["sc"].astype(np.int64)
+    L = len(x)
+    rows = list(x) + [20] * ((-L) % pad if L else pad)
+    R = np.full(M, -128, np.int64)
+    run = -128
+    for r in rows:
+        g = np.concatenate(([-128], R[:-1]))
+        R = np.maximum(-128, g + sc[r])                # no cap (I2)
+        run = max(run, int(R.max()))
+    return (127, 1) if run >= 127 else (run, 0)
+
+
+def test_msv_kernel_reformulation_matches_oracle():
+    rng = np.random.default_rng(21)
+    regimes = {"ovf": 0, "j": 0, "plain": 0}
+    for trial in range(40):
+        M = int(rng.choice([1, 3, 16, 48, 130]))
+        emis = synth.sample_emissions(rng, M)
+        prof = q.quantize(emis, synth.BG)
+        db = synth.random_db(rng, 12, 0, 200)
+        synth.implant(rng, db.res, db.offsets, [emis], 0.4)
+        for sidx in range(db.n):
+            x = db.seq(sidx)
+            exp = oracle.msv_seq(prof, x)
+            for tile in (4, 8, 32):
+                assert model_msv(prof, x, tile) == exp, (trial, sidx, tile)
+            regimes["ovf" if exp[1] else ("j" if exp[0] > q.BASE else "plain")] += 1
+    assert min(regimes.values()) > 3, regimes
+
+
+def test_ssv_kernel_reformulation_matches_oracle():
+    rng = np.random.default_rng(22)
+    nov = 0
+    for trial in range(40):
+        M = int(rng.choice([1, 3, 16, 48, 130]))
+        emis = synth.sample_emissions(rng, M)
+        prof = q.quantize(emis, synth.BG)
+        db = synth.random_db(rng, 12, 0, 200)
+        synth.implant(rng, db.res, db.offsets, [emis], 0.4)
+        for sidx in range(db.n):
+            x = db.seq(sidx)
+            exp = oracle.ssv_seq(prof, x)
+            assert model_ssv(prof, x) == exp
+            nov += exp[1]
+    assert nov > 3
