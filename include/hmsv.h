@@ -1,0 +1,151 @@
+/*
+ * hmsv: MSV and SSV profile-HMM filters for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only.  "host" pointers are ordinary CPU
+ * memory; "device" pointers are gfx950 global memory (for instance the data
+ * pointer of a torch tensor on a ROCm device).  All calls that take a stream
+ * are asynchronous on that stream; their outputs are valid once the stream
+ * has completed the call.  No call throws; every call returns an hmsv_status
+ * (0 = success, negative = error), and hmsv_strerror() names it.
+ *
+ * What is computed: the multiple-segment (MSV) and single-segment (SSV)
+ * ungapped Viterbi filters of HMMER3's pipeline (paper Sec. 2.1), scoring
+ * one quantized profile against every sequence of a packed database with
+ * 8-bit saturating arithmetic: unsigned with an offset ("dbias") for MSV
+ * (Alg. 2), signed with -inf = -128 for SSV (Alg. 7).  Results are the raw
+ * 8-bit filter scores and overflow flags, one per database sequence, in the
+ * caller's original sequence order.
+ */
+#ifndef HMSV_H
+#define HMSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+typedef int hmsv_status;
+#define HMSV_OK            0
+#define HMSV_EINVAL       -1   /* bad argument (null pointer, size, code range) */
+#define HMSV_EUNSUPPORTED -2   /* valid but beyond this build's limits */
+#define HMSV_ENOMEM       -3   /* device or host allocation failed */
+#define HMSV_EDEVICE      -4   /* a HIP runtime call failed */
+#define HMSV_ENOKERNEL    -5   /* no kernel instantiated for the requested plan */
+
+const char *hmsv_strerror(hmsv_status s);
+
+/* ---- model constants (MSV model of paper Sec. 2.1, Fig. 1) ------------- */
+#define HMSV_K        20    /* scoring amino acids, codes 0..19 (ACDEFGHIKLMNPQRSTVWY) */
+#define HMSV_KP       32    /* table rows: codes 20..31 are non-scoring (Alg. 4's 32-entry table) */
+#define HMSV_BASE    190    /* N/J level of the MSV special states */
+#define HMSV_TEC       3    /* E->J and E->C cost, -round(3 log2 1/2) */
+#define HMSV_MAX_M  3840    /* longest profile: the LDS table (21 x 3840 x 2 B) fits 160 KiB */
+#define HMSV_MAX_BIAS 64    /* dbias bound under which the kernels may omit the 255 cap */
+
+/* Uniform local-entry cost of a length-M profile: -round(3 log2(2/(M(M+1)))),
+ * rounding half away from zero.  M >= 1.  Returns -1 for M < 1. */
+int32_t hmsv_tbm(int32_t M);
+
+/* Length-model move cost for a target of length L: -round(3 log2(3/(L+3))).
+ * L >= 0.  Returns -1 for L < 0. */
+int32_t hmsv_tjb(int64_t L);
+
+/* ---- quantization (host) ----------------------------------------------
+ * Turns per-node match emission probabilities into the 8-bit tables of the
+ * MSV (Alg. 2 sigma/dbias) and SSV (Alg. 7) kernels:
+ *   r_k(x)    = round(3 log2(emis[k][x] / bg[x])) for x < 20 (-inf if emis = 0)
+ *   dbias     = max_{k,x} r_k(x)
+ *   cost[x][k]= min(255, dbias - r_k(x)) for x < 20, 255 for x >= 20
+ *   sc[x][k]  = max(-128, dbias - cost[x][k])
+ * emis: host, [M][20] float64, row k = node k+1, columns in code order.
+ * bg:   host, [20] float64 background frequencies, all > 0.
+ * cost: host, [32][M] uint8 out (residue-major).  sc: host, [32][M] int8 out.
+ * dbias: host, out.  Fails with HMSV_EINVAL on null pointers, M out of
+ * [1, HMSV_MAX_M], non-finite or negative probabilities, or bg <= 0. */
+hmsv_status hmsv_quantize(const double *emis, const double *bg, int32_t M,
+                          uint8_t *cost, int8_t *sc, int32_t *dbias);
+
+/* ---- profile ------------------------------------------------------------
+ * A quantized profile whose tables live in caller-owned device memory.
+ * cost (MSV) and sc (SSV) are [32][M] residue-major, as hmsv_quantize writes
+ * them; rows 20..31 must all equal row 20 (non-scoring: 255 and -128).  The
+ * library only reads them.  Either table may be NULL if that filter is not
+ * used.  Preconditions checked on the host: 1 <= M <= HMSV_MAX_M and
+ * 0 <= dbias <= HMSV_MAX_BIAS. */
+typedef struct {
+    int32_t M;
+    int32_t dbias;
+    const uint8_t *cost;   /* device */
+    const int8_t *sc;      /* device */
+} hmsv_profile;
+
+/* ---- packed database ----------------------------------------------------
+ * Opaque, device-resident copy of a sequence database, in the layout the
+ * kernels stream (sequences ordered longest first, each padded to a whole
+ * number of 4-residue words, with its length-model cost tjb(L) alongside).
+ * It owns its device memory until hmsv_db_destroy.  This replaces the
+ * paper's warp-based sequence blocks (Sec. 3.2, Alg. 1): sequences are
+ * handed to lane groups dynamically instead of being pre-packed per warp.
+ *
+ * res:     host, concatenated residue codes (uint8, each < 32).
+ * offsets: host, [nseq+1] int64, sequence i = res[offsets[i] .. offsets[i+1]).
+ * Synchronous.  Fails with HMSV_EINVAL on null pointers, decreasing offsets
+ * or codes >= 32; HMSV_EUNSUPPORTED if the packed size reaches 2^32 bytes or
+ * nseq >= 2^31. */
+typedef struct hmsv_db hmsv_db;
+hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t nseq,
+                           hmsv_db **out);
+void hmsv_db_destroy(hmsv_db *db);
+int64_t hmsv_db_nseq(const hmsv_db *db);
+int64_t hmsv_db_residues(const hmsv_db *db);     /* real residues (no padding) */
+int64_t hmsv_db_padded_rows(const hmsv_db *db);  /* rows the kernels run */
+
+/* ---- launch plan --------------------------------------------------------
+ * How one filter call maps onto the GPU.  A lane group of G lanes (4..64)
+ * aligns one sequence; each lane holds Q packed pairs of nodes, so the
+ * group covers 2*G*Q >= M nodes.  64/G sequences share a wavefront (the
+ * paper's multi-sequence alignment, Sec. 3.1 tier 4).  waves_per_block
+ * wavefronts share one LDS copy of the profile; blocks = 0 picks a
+ * persistent grid of the resident maximum.  tile is the number of rows
+ * (multiple of 4) between checks of the MSV special states. */
+typedef struct {
+    int32_t G;
+    int32_t Q;
+    int32_t waves_per_block;
+    int32_t blocks;
+    int32_t tile;
+} hmsv_plan;
+
+/* The library's default plan for a filter ("msv" = 1, "ssv" = 0) and M. */
+hmsv_status hmsv_default_plan(int32_t is_msv, int32_t M, hmsv_plan *plan);
+
+/* Device workspace needed by a scoring call (bytes, small and fixed). */
+size_t hmsv_workspace_bytes(void);
+
+/* ---- scoring -----------------------------------------------------------
+ * MSV (paper Alg. 2): score[i] = raw 8-bit MSV score of sequence i (the
+ * final scJ), flags[i] = 1 if the biased score saturated (then score = 255).
+ * SSV (paper Alg. 7): score[i] = best single-segment score in signed 8-bit
+ * (-128 = no positive segment), flags[i] = 1 on saturation (score = 127).
+ * score, flags: device, [nseq] each, written for every sequence.
+ * workspace: device, hmsv_workspace_bytes() bytes, caller-owned; its content
+ * need not be initialised; calls that share a workspace must be ordered on
+ * one stream.  plan: NULL for the default.  The call allocates nothing.
+ * Fails with HMSV_EINVAL on null pointers or a profile outside its
+ * preconditions, HMSV_ENOKERNEL if the plan was not instantiated,
+ * HMSV_EDEVICE if the launch fails. */
+hmsv_status hmsv_msv_score(const hmsv_profile *prof, const hmsv_db *db,
+                           uint8_t *score, uint8_t *flags, void *workspace,
+                           const hmsv_plan *plan, hipStream_t stream);
+hmsv_status hmsv_ssv_score(const hmsv_profile *prof, const hmsv_db *db,
+                           int8_t *score, uint8_t *flags, void *workspace,
+                           const hmsv_plan *plan, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HMSV_H */

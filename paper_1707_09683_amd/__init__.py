@@ -1,0 +1,236 @@
+"""MSV / SSV profile-HMM filters on AMD Instinct MI355X (gfx950).
+
+A thin ctypes binding over ``libhmsv.so`` (C ABI in ``include/hmsv.h``).
+This module only marshals arguments: quantization, database packing and both
+filters run in the native library and its HIP kernels.  PyTorch supplies
+device memory (output and table tensors) and streams.
+
+If ``libhmsv.so`` has not been built, importing this package raises
+ImportError: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # must load before libhmsv so both share one HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhmsv.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -m paper_1707_09683_amd.build` (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK = 0
+K = 20
+KP = 32
+BASE = 190
+TEC = 3
+MAX_M = 3840
+MAX_BIAS = 64
+
+
+class HmsvError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        msg = _lib.hmsv_strerror(status).decode()
+        super().__init__(f"{what}: {msg} ({status})")
+        self.status = status
+
+
+class _CProfile(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("dbias", ctypes.c_int32),
+                ("cost", ctypes.c_void_p), ("sc", ctypes.c_void_p)]
+
+
+class Plan(ctypes.Structure):
+    """Launch plan (hmsv_plan): group width G, registers per lane Q,
+    waves per block, blocks (0 = persistent), MSV special-state tile."""
+    _fields_ = [("G", ctypes.c_int32), ("Q", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("tile", ctypes.c_int32)]
+
+    def __repr__(self):
+        return (f"Plan(G={self.G}, Q={self.Q}, waves_per_block={self.waves_per_block}, "
+                f"blocks={self.blocks}, tile={self.tile})")
+
+    def as_tuple(self):
+        return (self.G, self.Q, self.waves_per_block, self.blocks, self.tile)
+
+
+_P = ctypes.c_void_p
+_i32, _i64 = ctypes.c_int32, ctypes.c_int64
+_lib.hmsv_strerror.restype = ctypes.c_char_p
+_lib.hmsv_strerror.argtypes = [ctypes.c_int]
+_lib.hmsv_tbm.restype = _i32
+_lib.hmsv_tbm.argtypes = [_i32]
+_lib.hmsv_tjb.restype = _i32
+_lib.hmsv_tjb.argtypes = [_i64]
+_lib.hmsv_quantize.restype = ctypes.c_int
+_lib.hmsv_quantize.argtypes = [_P, _P, _i32, _P, _P, ctypes.POINTER(_i32)]
+_lib.hmsv_db_create.restype = ctypes.c_int
+_lib.hmsv_db_create.argtypes = [_P, _P, _i64, ctypes.POINTER(_P)]
+_lib.hmsv_db_destroy.restype = None
+_lib.hmsv_db_destroy.argtypes = [_P]
+for _f in ("hmsv_db_nseq", "hmsv_db_residues", "hmsv_db_padded_rows"):
+    getattr(_lib, _f).restype = _i64
+    getattr(_lib, _f).argtypes = [_P]
+_lib.hmsv_default_plan.restype = ctypes.c_int
+_lib.hmsv_default_plan.argtypes = [_i32, _i32, ctypes.POINTER(Plan)]
+_lib.hmsv_workspace_bytes.restype = ctypes.c_size_t
+_lib.hmsv_workspace_bytes.argtypes = []
+for _f in ("hmsv_msv_score", "hmsv_ssv_score"):
+    getattr(_lib, _f).restype = ctypes.c_int
+    getattr(_lib, _f).argtypes = [ctypes.POINTER(_CProfile), _P, _P, _P, _P,
+                                  ctypes.POINTER(Plan), _P]
+
+EXPORTED = ("hmsv_strerror", "hmsv_tbm", "hmsv_tjb", "hmsv_quantize", "hmsv_db_create",
+            "hmsv_db_destroy", "hmsv_db_nseq", "hmsv_db_residues", "hmsv_db_padded_rows",
+            "hmsv_default_plan", "hmsv_workspace_bytes", "hmsv_msv_score", "hmsv_ssv_score")
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise HmsvError(rc, what)
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def tbm(M: int) -> int:
+    return int(_lib.hmsv_tbm(int(M)))
+
+
+def tjb(L: int) -> int:
+    return int(_lib.hmsv_tjb(int(L)))
+
+
+def quantize(emissions, bg):
+    """Host quantization (hmsv_quantize).  Returns dict(cost uint8 [32, M],
+    sc int8 [32, M], dbias, M)."""
+    e = np.ascontiguousarray(emissions, dtype=np.float64)
+    b = np.ascontiguousarray(bg, dtype=np.float64)
+    if e.ndim != 2 or e.shape[1] != K or b.shape != (K,):
+        raise ValueError("emissions must be [M, 20] and bg [20]")
+    M = e.shape[0]
+    cost = np.empty((KP, M), np.uint8)
+    sc = np.empty((KP, M), np.int8)
+    dbias = _i32(0)
+    _check(_lib.hmsv_quantize(_np_ptr(e), _np_ptr(b), M, _np_ptr(cost), _np_ptr(sc),
+                              ctypes.byref(dbias)), "hmsv_quantize")
+    return {"cost": cost, "sc": sc, "dbias": int(dbias.value), "M": M}
+
+
+class Profile:
+    """A quantized profile with its tables in device memory (torch tensors)."""
+
+    def __init__(self, cost: torch.Tensor, sc: torch.Tensor, dbias: int):
+        if cost.dtype != torch.uint8 or sc.dtype != torch.int8:
+            raise TypeError("cost must be uint8 and sc int8")
+        if cost.shape != sc.shape or cost.shape[0] != KP:
+            raise ValueError("tables must both be [32, M]")
+        self.cost = cost.contiguous()
+        self.sc = sc.contiguous()
+        self.M = int(cost.shape[1])
+        self.dbias = int(dbias)
+        self.device = self.cost.device
+        self._c = _CProfile(self.M, self.dbias, self.cost.data_ptr(), self.sc.data_ptr())
+
+    @classmethod
+    def from_emissions(cls, emissions, bg, device="cuda"):
+        q = quantize(emissions, bg)
+        return cls(torch.from_numpy(q["cost"]).to(device), torch.from_numpy(q["sc"]).to(device),
+                   q["dbias"])
+
+
+class Database:
+    """Packed, device-resident sequence database (hmsv_db)."""
+
+    def __init__(self, residues, offsets, device="cuda"):
+        res = np.ascontiguousarray(residues, dtype=np.uint8)
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        if off.ndim != 1 or len(off) < 1:
+            raise ValueError("offsets must be [nseq + 1]")
+        self.device = torch.device(device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.hmsv_db_create(_np_ptr(res) if res.size else None, _np_ptr(off),
+                                       len(off) - 1, ctypes.byref(h)), "hmsv_db_create")
+        self._h = h
+        self.nseq = int(_lib.hmsv_db_nseq(h))
+        self.residues = int(_lib.hmsv_db_residues(h))
+        self.padded_rows = int(_lib.hmsv_db_padded_rows(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hmsv_db_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def default_plan(filt: str, M: int) -> Plan:
+    p = Plan()
+    _check(_lib.hmsv_default_plan(1 if filt == "msv" else 0, int(M), ctypes.byref(p)),
+           "hmsv_default_plan")
+    return p
+
+
+def make_plan(G, Q, waves_per_block=4, blocks=0, tile=32) -> Plan:
+    return Plan(int(G), int(Q), int(waves_per_block), int(blocks), int(tile))
+
+
+def workspace_bytes() -> int:
+    return int(_lib.hmsv_workspace_bytes())
+
+
+def new_workspace(device="cuda") -> torch.Tensor:
+    return torch.zeros(workspace_bytes(), dtype=torch.uint8, device=device)
+
+
+def _score(filt, profile: Profile, db: Database, score, flags, workspace, plan, stream):
+    dev = profile.device
+    n = db.nseq
+    sdt = torch.uint8 if filt == "msv" else torch.int8
+    if score is None:
+        score = torch.empty(n, dtype=sdt, device=dev)
+    if flags is None:
+        flags = torch.empty(n, dtype=torch.uint8, device=dev)
+    if workspace is None:
+        workspace = new_workspace(dev)
+    if score.dtype != sdt or flags.dtype != torch.uint8:
+        raise TypeError("score/flags dtype")
+    if score.numel() < n or flags.numel() < n or not score.is_contiguous() \
+            or not flags.is_contiguous():
+        raise ValueError("score/flags must be contiguous with >= nseq entries")
+    if workspace.numel() * workspace.element_size() < workspace_bytes():
+        raise ValueError("workspace too small")
+    for t in (score, flags, workspace):
+        if t.device != dev:
+            raise ValueError("all tensors must be on the profile's device")
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    fn = _lib.hmsv_msv_score if filt == "msv" else _lib.hmsv_ssv_score
+    with torch.cuda.device(dev):
+        _check(fn(ctypes.byref(profile._c), db._h, score.data_ptr(), flags.data_ptr(),
+                  workspace.data_ptr(), ctypes.byref(plan) if plan is not None else None,
+                  ctypes.c_void_p(stream.cuda_stream)), f"hmsv_{filt}_score")
+    return score, flags
+
+
+def msv_score(profile, db, score=None, flags=None, workspace=None, plan=None, stream=None):
+    """MSV filter (paper Alg. 2): uint8 scores and overflow flags per sequence."""
+    return _score("msv", profile, db, score, flags, workspace, plan, stream)
+
+
+def ssv_score(profile, db, score=None, flags=None, workspace=None, plan=None, stream=None):
+    """SSV filter (paper Alg. 7): int8 scores and overflow flags per sequence."""
+    return _score("ssv", profile, db, score, flags, workspace, plan, stream)

@@ -1,0 +1,111 @@
+"""Build libhmsv.so for gfx950 with hipcc (in-tree).
+
+The kernel template is compiled once per (group width G, range of Q) so the
+instantiations build in parallel; the host code is one more translation
+unit.  Usage: ``python -m paper_1707_09683_amd.build [--jobs N] [--incremental]``.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import hashlib
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+OBJ = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libhmsv.so")
+ARCH = "gfx950"
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+COMMON = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-I", CSRC, "-I", INCLUDE, "-Wno-unused-command-line-argument"]
+
+# (G, largest Q).  The LDS table is 21 rows x G x Q dwords and must fit in
+# 160 KiB, which caps G = 64 at Q = 30 (profiles up to 3840 nodes).
+GROUPS = ((4, 32), (8, 32), (16, 32), (32, 32), (64, 30))
+QCHUNK = 4
+
+
+def kernel_units():
+    units = []
+    for G, qmax in GROUPS:
+        for lo in range(1, qmax + 1, QCHUNK):
+            hi = min(qmax, lo + QCHUNK - 1)
+            units.append((G, lo, hi))
+    return units
+
+
+def _deps_hash(extra):
+    h = hashlib.sha1()
+    for f in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    with open(os.path.join(INCLUDE, "hmsv.h"), "rb") as fh:
+        h.update(fh.read())
+    h.update(" ".join(COMMON + extra).encode())
+    return h.hexdigest()
+
+
+def _compile(cmd, out, stamp, incremental):
+    if incremental and os.path.exists(out) and os.path.exists(out + ".stamp"):
+        if open(out + ".stamp").read() == stamp:
+            return out, 0.0, ""
+    import time
+    t0 = time.time()
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{p.stderr}")
+    with open(out + ".stamp", "w") as fh:
+        fh.write(stamp)
+    return out, time.time() - t0, p.stderr
+
+
+def build(jobs: int | None = None, incremental: bool = False, verbose: bool = False) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = jobs or max(1, min(16, os.cpu_count() or 1))
+    tasks = []
+    host_obj = os.path.join(OBJ, "hmsv_host.o")
+    host_cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, "hmsv_host.cpp"),
+                "-o", host_obj]
+    tasks.append((host_cmd, host_obj, _deps_hash(["host"])))
+    for G, lo, hi in kernel_units():
+        obj = os.path.join(OBJ, f"kernels_g{G}_q{lo}_{hi}.o")
+        defs = [f"-DHMSV_G={G}", f"-DHMSV_QLO={lo}", f"-DHMSV_QHI={hi}"]
+        cmd = [HIPCC, *COMMON, *defs, "-c", os.path.join(CSRC, "kernels.hip"), "-o", obj]
+        tasks.append((cmd, obj, _deps_hash(defs)))
+    objs = []
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = [ex.submit(_compile, c, o, s, incremental) for c, o, s in tasks]
+        for f in futs:
+            o, dt, err = f.result()
+            objs.append(o)
+            if verbose:
+                print(f"  {os.path.basename(o)}: {dt:.1f}s", flush=True)
+    tmp = LIB + ".tmp"
+    subprocess.check_call([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
+                           *objs])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def clean():
+    shutil.rmtree(OBJ, ignore_errors=True)
+    if os.path.exists(LIB):
+        os.remove(LIB)
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--incremental", action="store_true")
+    ap.add_argument("-v", "--verbose", action="store_true")
+    a = ap.parse_args()
+    print(build(a.jobs, a.incremental, a.verbose))
+    sys.exit(0)

@@ -1,0 +1,346 @@
+// Host side of libhmsv: quantization, database packing, plan selection and
+// kernel dispatch.  The C ABI is declared in include/hmsv.h.
+#include "hmsv.h"
+#include "hmsv_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <vector>
+
+using namespace hmsv;
+
+namespace hmsv {
+int register_kernels(const KernelEntry *entries, int n);
+hipError_t launch_zero(uint32_t *p, int n, hipStream_t s);
+}
+
+struct hmsv_db {
+    int64_t nseq = 0;
+    int64_t residues = 0;
+    int64_t rows = 0;
+    uint8_t *d_res = nullptr;
+    SeqRec *d_seqs = nullptr;
+    uint32_t pad_off = 0;
+    int device = 0;
+};
+
+namespace {
+
+// Round half away from zero of a finite double.
+double rhaz(double v) {
+    double t = std::trunc(v);
+    if (std::fabs(v - t) >= 0.5) t += (v > 0 ? 1.0 : -1.0);
+    return t;
+}
+
+// Third-bit cost of a probability p in (0, 1]: -round(3 log2 p).
+int32_t third_bit_cost(double p) { return (int32_t)(-rhaz(3.0 * std::log2(p))); }
+
+struct Registry {
+    std::vector<KernelEntry> entries;
+    const KernelEntry *find(int is_msv, int G, int Q) const {
+        for (const auto &e : entries)
+            if (e.is_msv == is_msv && e.G == G && e.Q == Q) return &e;
+        return nullptr;
+    }
+};
+
+Registry &registry() {
+    static Registry r;
+    return r;
+}
+
+__global__ void zero_kernel(uint32_t *p, int n) {
+    int i = threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// Persistent-grid size per (kernel, waves_per_block), measured once per device.
+struct OccKey { const KernelEntry *e; int wpb; int dev; };
+std::mutex g_occ_mu;
+std::vector<std::pair<OccKey, int>> g_occ;
+
+int resident_blocks(const KernelEntry *e, int wpb) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    {
+        std::lock_guard<std::mutex> lk(g_occ_mu);
+        for (auto &p : g_occ)
+            if (p.first.e == e && p.first.wpb == wpb && p.first.dev == dev) return p.second;
+    }
+    int per_cu = e->occupancy(wpb);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    int blocks = per_cu * cus;
+    std::lock_guard<std::mutex> lk(g_occ_mu);
+    g_occ.push_back({{e, wpb, dev}, blocks});
+    return blocks;
+}
+
+hmsv_status check_profile(const hmsv_profile *p, int is_msv) {
+    if (!p) return HMSV_EINVAL;
+    if (p->M < 1) return HMSV_EINVAL;
+    if (p->M > HMSV_MAX_M) return HMSV_EUNSUPPORTED;
+    if (p->dbias < 0 || p->dbias > HMSV_MAX_BIAS) return HMSV_EINVAL;
+    if (is_msv && !p->cost) return HMSV_EINVAL;
+    if (!is_msv && !p->sc) return HMSV_EINVAL;
+    return HMSV_OK;
+}
+
+hmsv_status check_plan(const hmsv_plan *pl, int M) {
+    if (pl->G < 1 || pl->G > 64 || (64 % pl->G) != 0) return HMSV_EINVAL;
+    if (pl->Q < 1) return HMSV_EINVAL;
+    if ((int64_t)2 * pl->G * pl->Q < M) return HMSV_EINVAL;
+    if (pl->waves_per_block < 1 || pl->waves_per_block > 8) return HMSV_EINVAL;
+    if (pl->blocks < 0) return HMSV_EINVAL;
+    if (pl->tile < 4 || (pl->tile % 4) != 0) return HMSV_EINVAL;
+    if (lds_bytes(pl->G, pl->Q) > (size_t)kLdsBytes) return HMSV_EUNSUPPORTED;
+    return HMSV_OK;
+}
+
+hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db,
+                         uint8_t *score, uint8_t *flags, void *workspace,
+                         const hmsv_plan *plan_in, hipStream_t stream) {
+    hmsv_status st = check_profile(prof, is_msv);
+    if (st != HMSV_OK) return st;
+    if (!db || !score || !flags || !workspace) return HMSV_EINVAL;
+    hmsv_plan plan;
+    if (plan_in) {
+        plan = *plan_in;
+    } else {
+        st = hmsv_default_plan(is_msv, prof->M, &plan);
+        if (st != HMSV_OK) return st;
+    }
+    st = check_plan(&plan, prof->M);
+    if (st != HMSV_OK) return st;
+    const KernelEntry *e = registry().find(is_msv, plan.G, plan.Q);
+    if (!e) return HMSV_ENOKERNEL;
+    if (db->nseq == 0) return HMSV_OK;
+
+    KArgs a;
+    a.cost = prof->cost;
+    a.sc = prof->sc;
+    a.M = prof->M;
+    a.dbias = prof->dbias;
+    a.tbm = hmsv_tbm(prof->M);
+    a.tile_blocks = plan.tile / 4;
+    a.res = db->d_res;
+    a.seqs = db->d_seqs;
+    a.nseq = (int32_t)db->nseq;
+    a.pad_off = db->pad_off;
+    a.score = score;
+    a.flag = flags;
+    a.counter = (uint32_t *)workspace;
+
+    int blocks = plan.blocks;
+    if (blocks == 0) {
+        blocks = resident_blocks(e, plan.waves_per_block);
+        if (blocks <= 0) return HMSV_EDEVICE;
+        // no more wavefronts than there are lane groups' worth of sequences
+        int64_t groups_per_block = (int64_t)plan.waves_per_block * (64 / plan.G);
+        int64_t need = (db->nseq + groups_per_block - 1) / groups_per_block;
+        if (need < blocks) blocks = (int)need;
+    }
+    if (launch_zero(a.counter, 4, stream) != hipSuccess) return HMSV_EDEVICE;
+    if (e->launch(a, plan.waves_per_block, blocks, stream) != hipSuccess) return HMSV_EDEVICE;
+    return HMSV_OK;
+}
+
+}  // namespace
+
+namespace hmsv {
+int register_kernels(const KernelEntry *entries, int n) {
+    registry().entries.insert(registry().entries.end(), entries, entries + n);
+    return n;
+}
+
+hipError_t launch_zero(uint32_t *p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+}  // namespace hmsv
+
+extern "C" {
+
+const char *hmsv_strerror(hmsv_status s) {
+    switch (s) {
+        case HMSV_OK: return "success";
+        case HMSV_EINVAL: return "invalid argument";
+        case HMSV_EUNSUPPORTED: return "unsupported size";
+        case HMSV_ENOMEM: return "out of memory";
+        case HMSV_EDEVICE: return "HIP runtime error";
+        case HMSV_ENOKERNEL: return "no kernel instantiated for this plan";
+        default: return "unknown status";
+    }
+}
+
+int32_t hmsv_tbm(int32_t M) {
+    if (M < 1) return -1;
+    double m = (double)M;
+    return third_bit_cost(2.0 / (m * (m + 1.0)));
+}
+
+int32_t hmsv_tjb(int64_t L) {
+    if (L < 0) return -1;
+    return third_bit_cost(3.0 / ((double)L + 3.0));
+}
+
+hmsv_status hmsv_quantize(const double *emis, const double *bg, int32_t M, uint8_t *cost,
+                          int8_t *sc, int32_t *dbias) {
+    if (!emis || !bg || !cost || !sc || !dbias) return HMSV_EINVAL;
+    if (M < 1 || M > HMSV_MAX_M) return HMSV_EINVAL;
+    for (int x = 0; x < HMSV_K; ++x)
+        if (!(bg[x] > 0.0) || !std::isfinite(bg[x])) return HMSV_EINVAL;
+    const int64_t kNegInf = INT64_MIN / 4;
+    std::vector<int64_t> r((size_t)M * HMSV_K);
+    int64_t best = kNegInf;
+    for (int k = 0; k < M; ++k) {
+        for (int x = 0; x < HMSV_K; ++x) {
+            double e = emis[(size_t)k * HMSV_K + x];
+            if (!(e >= 0.0) || !std::isfinite(e)) return HMSV_EINVAL;
+            int64_t v = kNegInf;
+            if (e > 0.0) v = (int64_t)rhaz(3.0 * std::log2(e / bg[x]));
+            r[(size_t)k * HMSV_K + x] = v;
+            best = std::max(best, v);
+        }
+    }
+    if (best == kNegInf) return HMSV_EINVAL;
+    for (int x = 0; x < HMSV_KP; ++x) {
+        for (int k = 0; k < M; ++k) {
+            int64_t c = 255;
+            if (x < HMSV_K) c = std::min<int64_t>(255, best - r[(size_t)k * HMSV_K + x]);
+            cost[(size_t)x * M + k] = (uint8_t)c;
+            sc[(size_t)x * M + k] = (int8_t)std::max<int64_t>(-128, best - c);
+        }
+    }
+    *dbias = (int32_t)best;
+    return HMSV_OK;
+}
+
+hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t nseq,
+                           hmsv_db **out) {
+    if (!out || !offsets || nseq < 0) return HMSV_EINVAL;
+    *out = nullptr;
+    if (nseq > 0 && !res && offsets[nseq] > offsets[0]) return HMSV_EINVAL;
+    if (nseq >= ((int64_t)1 << 31)) return HMSV_EUNSUPPORTED;
+    std::vector<int64_t> len((size_t)nseq);
+    int64_t residues = 0;
+    for (int64_t i = 0; i < nseq; ++i) {
+        len[i] = offsets[i + 1] - offsets[i];
+        if (len[i] < 0) return HMSV_EINVAL;
+        residues += len[i];
+    }
+    for (int64_t i = 0; i < nseq; ++i) {
+        const uint8_t *p = res + offsets[i];
+        for (int64_t t = 0; t < len[i]; ++t)
+            if (p[t] >= HMSV_KP) return HMSV_EINVAL;
+    }
+    // Longest first: the dynamic queue then ends with short sequences.
+    std::vector<int64_t> order((size_t)nseq);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return len[a] > len[b]; });
+    std::vector<SeqRec> recs((size_t)nseq);
+    uint64_t total = 0, rows = 0;
+    for (int64_t t = 0; t < nseq; ++t) {
+        int64_t i = order[t];
+        uint64_t r = (uint64_t)std::max<int64_t>(4, (len[i] + 3) & ~(int64_t)3);
+        recs[t].off = (uint32_t)total;
+        recs[t].rows = (uint32_t)r;
+        recs[t].id = (uint32_t)i;
+        recs[t].tjb = (uint32_t)hmsv_tjb(len[i]);
+        total += r;
+        rows += r;
+        if (total >= ((uint64_t)1 << 32) - 64) return HMSV_EUNSUPPORTED;
+    }
+    const uint32_t pad_off = (uint32_t)total;
+    const size_t bytes = (size_t)total + 64;
+    std::vector<uint8_t> packed(bytes, kInvalidCode);
+    for (int64_t t = 0; t < nseq; ++t) {
+        int64_t i = order[t];
+        const uint8_t *p = res + offsets[i];
+        uint8_t *d = packed.data() + recs[t].off;
+        for (int64_t k = 0; k < len[i]; ++k) d[k] = p[k] < HMSV_K ? p[k] : kInvalidCode;
+    }
+    hmsv_db *db = new (std::nothrow) hmsv_db;
+    if (!db) return HMSV_ENOMEM;
+    db->nseq = nseq;
+    db->residues = residues;
+    db->rows = (int64_t)rows;
+    db->pad_off = pad_off;
+    if (hipGetDevice(&db->device) != hipSuccess) { delete db; return HMSV_EDEVICE; }
+    if (hipMalloc(&db->d_res, bytes) != hipSuccess) { delete db; return HMSV_ENOMEM; }
+    if (hipMalloc(&db->d_seqs, sizeof(SeqRec) * (size_t)std::max<int64_t>(1, nseq)) != hipSuccess) {
+        hipFree(db->d_res);
+        delete db;
+        return HMSV_ENOMEM;
+    }
+    if (hipMemcpy(db->d_res, packed.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        (nseq > 0 && hipMemcpy(db->d_seqs, recs.data(), sizeof(SeqRec) * (size_t)nseq,
+                               hipMemcpyHostToDevice) != hipSuccess)) {
+        hmsv_db_destroy(db);
+        return HMSV_EDEVICE;
+    }
+    *out = db;
+    return HMSV_OK;
+}
+
+void hmsv_db_destroy(hmsv_db *db) {
+    if (!db) return;
+    if (db->d_res) hipFree(db->d_res);
+    if (db->d_seqs) hipFree(db->d_seqs);
+    delete db;
+}
+
+int64_t hmsv_db_nseq(const hmsv_db *db) { return db ? db->nseq : -1; }
+int64_t hmsv_db_residues(const hmsv_db *db) { return db ? db->residues : -1; }
+int64_t hmsv_db_padded_rows(const hmsv_db *db) { return db ? db->rows : -1; }
+
+hmsv_status hmsv_default_plan(int32_t is_msv, int32_t M, hmsv_plan *plan) {
+    if (!plan) return HMSV_EINVAL;
+    if (M < 1) return HMSV_EINVAL;
+    if (M > HMSV_MAX_M) return HMSV_EUNSUPPORTED;
+    // Lane-ops per cell ~ G * (ops_per_pair * Q + per_row) / M: pick the
+    // group width that minimises it among instantiated kernels.
+    const double per_pair = is_msv ? 3.0 : 2.0;
+    const double per_row = 8.0;
+    double best = 1e30;
+    hmsv_plan bp{};
+    for (int G : {4, 8, 16, 32, 64}) {
+        int Q = (M + 2 * G - 1) / (2 * G);
+        if (!registry().find(is_msv, G, Q)) continue;
+        double cost = G * (per_pair * Q + per_row);
+        if (cost < best) {
+            best = cost;
+            bp.G = G;
+            bp.Q = Q;
+        }
+    }
+    if (best >= 1e30) return HMSV_ENOKERNEL;
+    bp.waves_per_block = 4;
+    bp.blocks = 0;
+    bp.tile = 32;
+    *plan = bp;
+    return HMSV_OK;
+}
+
+size_t hmsv_workspace_bytes(void) { return 256; }
+
+hmsv_status hmsv_msv_score(const hmsv_profile *prof, const hmsv_db *db, uint8_t *score,
+                           uint8_t *flags, void *workspace, const hmsv_plan *plan,
+                           hipStream_t stream) {
+    return score_common(1, prof, db, score, flags, workspace, plan, stream);
+}
+
+hmsv_status hmsv_ssv_score(const hmsv_profile *prof, const hmsv_db *db, int8_t *score,
+                           uint8_t *flags, void *workspace, const hmsv_plan *plan,
+                           hipStream_t stream) {
+    return score_common(0, prof, db, (uint8_t *)score, flags, workspace, plan, stream);
+}
+
+}  // extern "C"

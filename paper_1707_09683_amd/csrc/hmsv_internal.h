@@ -1,0 +1,59 @@
+// Internal declarations shared by the host side of the library and the
+// kernel translation units.  Not part of the public ABI.
+#pragma once
+#include <stdint.h>
+#include <stddef.h>
+#include <hip/hip_runtime.h>
+
+namespace hmsv {
+
+// Table rows staged in LDS: the 20 amino acids plus one non-scoring row.
+// The database packer maps every code 20..31 to 20.
+constexpr int kRows = 21;
+constexpr uint8_t kInvalidCode = 20;
+constexpr int kLdsBytes = 160 * 1024;
+
+// One database sequence in processing order (longest first).
+struct SeqRec {
+    uint32_t off;    // byte offset of its first residue in the packed stream
+    uint32_t rows;   // rows to run: length rounded up to a multiple of 4, at least 4
+    uint32_t id;     // index in the caller's original order
+    uint32_t tjb;    // length-model cost tjb(L) of its true length
+};
+
+struct KArgs {
+    const uint8_t *cost;   // [32][M] MSV costs (device)
+    const int8_t *sc;      // [32][M] SSV scores (device)
+    int32_t M;
+    int32_t dbias;
+    int32_t tbm;
+    int32_t tile_blocks;   // rows per special-state check / 4
+    const uint8_t *res;    // packed residues
+    const SeqRec *seqs;
+    int32_t nseq;
+    uint32_t pad_off;      // offset of >= 16 non-scoring residues
+    uint8_t *score;
+    uint8_t *flag;
+    uint32_t *counter;     // work-queue head, zero at launch
+};
+
+typedef hipError_t (*LaunchFn)(const KArgs &, int waves_per_block, int blocks,
+                               hipStream_t);
+typedef int (*OccupancyFn)(int waves_per_block);
+
+struct KernelEntry {
+    int is_msv;
+    int G;
+    int Q;
+    LaunchFn launch;
+    OccupancyFn occupancy;
+};
+
+inline size_t lds_bytes(int G, int Q) { return (size_t)kRows * G * Q * 4; }
+
+// Each kernel translation unit registers its instantiations at load time.
+int register_kernels(const KernelEntry *entries, int n);
+
+hipError_t launch_zero(uint32_t *p, int n, hipStream_t s);
+
+}  // namespace hmsv

@@ -1,0 +1,115 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library must load, export every function include/hmsv.h declares, and
+reject bad arguments on the host before touching the device.  Its own
+quantizer and length-model constants are compared with the oracle's
+(independent implementations of the same definitions)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import quant as oq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hmsv.h")
+
+hm = pytest.importorskip("paper_1707_09683_amd")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hmsv_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(hm.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(hm.EXPORTED) == set(names)
+
+
+def test_constants_match_oracle():
+    for M in (1, 2, 3, 48, 100, 400, 1000, 2400, 3840):
+        assert hm.tbm(M) == oq.tbm(M)
+    for L in (0, 1, 2, 3, 20, 21, 45, 350, 1000, 35000, 10 ** 6):
+        assert hm.tjb(L) == oq.tjb(L)
+    assert hm.tbm(0) == -1 and hm.tjb(-1) == -1
+
+
+def test_quantizer_matches_oracle_bit_for_bit():
+    rng = np.random.default_rng(31)
+    for M in (1, 7, 48, 400, 1000, 2400, 3840):
+        e = synth.sample_emissions(rng, M)
+        a = hm.quantize(e, synth.BG)
+        b = oq.quantize(e, synth.BG)
+        assert a["dbias"] == b["bias"]
+        assert (a["cost"] == b["cost"]).all() and (a["sc"] == b["sc"]).all()
+
+
+def test_quantizer_rejects_bad_input():
+    e = np.full((4, 20), 0.05)
+    with pytest.raises(hm.HmsvError):
+        hm.quantize(e, np.zeros(20))
+    bad = e.copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(hm.HmsvError):
+        hm.quantize(bad, synth.BG)
+    bad[0, 0] = -0.1
+    with pytest.raises(hm.HmsvError):
+        hm.quantize(bad, synth.BG)
+    with pytest.raises(hm.HmsvError):
+        hm.quantize(np.full((3841, 20), 0.05), synth.BG)
+
+
+def test_db_create_validates_on_host():
+    P = ctypes.c_void_p
+    h = P()
+    res = np.array([1, 2, 32], np.uint8)          # code 32 is out of range
+    off = np.array([0, 3], np.int64)
+    rc = hm._lib.hmsv_db_create(hm._np_ptr(res), hm._np_ptr(off), 1, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    off = np.array([0, 2, 1], np.int64)           # decreasing offsets
+    res = np.array([1, 2, 3], np.uint8)
+    assert hm._lib.hmsv_db_create(hm._np_ptr(res), hm._np_ptr(off), 2, ctypes.byref(h)) == -1
+    assert hm._lib.hmsv_db_create(hm._np_ptr(res), None, 2, ctypes.byref(h)) == -1
+    assert hm._lib.hmsv_db_create(hm._np_ptr(res), hm._np_ptr(off), 2, None) == -1
+
+
+def test_score_rejects_bad_arguments_before_launch():
+    prof = hm._CProfile(0, 10, 1, 1)              # M = 0
+    ws = ctypes.c_void_p(1)
+    rc = hm._lib.hmsv_msv_score(ctypes.byref(prof), ctypes.c_void_p(1), 1, 1, ws, None, None)
+    assert rc == -1
+    prof = hm._CProfile(10, 65, 1, 1)             # dbias above the bound
+    assert hm._lib.hmsv_msv_score(ctypes.byref(prof), ctypes.c_void_p(1), 1, 1, ws, None,
+                                  None) == -1
+    prof = hm._CProfile(4000, 10, 1, 1)           # longer than HMSV_MAX_M
+    assert hm._lib.hmsv_ssv_score(ctypes.byref(prof), ctypes.c_void_p(1), 1, 1, ws, None,
+                                  None) == -2
+    prof = hm._CProfile(10, 10, 1, None)          # SSV table missing
+    assert hm._lib.hmsv_ssv_score(ctypes.byref(prof), ctypes.c_void_p(1), 1, 1, ws, None,
+                                  None) == -1
+    prof = hm._CProfile(100, 10, 1, 1)
+    bad_plan = hm.make_plan(8, 2)                 # covers 32 < 100 nodes
+    assert hm._lib.hmsv_msv_score(ctypes.byref(prof), ctypes.c_void_p(1), 1, 1, ws,
+                                  ctypes.byref(bad_plan), None) == -1
+    odd_plan = hm.make_plan(8, 7, tile=6)         # tile not a multiple of 4
+    assert hm._lib.hmsv_msv_score(ctypes.byref(prof), ctypes.c_void_p(1), 1, 1, ws,
+                                  ctypes.byref(odd_plan), None) == -1
+    assert hm._lib.hmsv_msv_score(ctypes.byref(prof), None, 1, 1, ws, None, None) == -1
+
+
+def test_default_plans_cover_every_length():
+    for filt in ("msv", "ssv"):
+        for M in list(range(1, 200)) + list(range(200, 3841, 37)) + [3840]:
+            p = hm.default_plan(filt, M)
+            assert 2 * p.G * p.Q >= M and 64 % p.G == 0
+    with pytest.raises(hm.HmsvError):
+        hm.default_plan("msv", 3841)

@@ -1,0 +1,141 @@
+"""GPU parity: every sequence's score and overflow flag, bit for bit, against the oracle.
+
+Both sides quantize the same float64 emissions independently (the library
+in C++, the oracle in numpy) and score the same seeded databases."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import quant as oq
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_09683_amd as m
+    return m
+
+
+def _gpu(hm, filt, emis, db, plan=None):
+    prof = hm.Profile.from_emissions(emis, synth.BG)
+    gdb = hm.Database(db.res, db.offsets)
+    fn = hm.msv_score if filt == "msv" else hm.ssv_score
+    s, f = fn(prof, gdb, plan=plan)
+    torch.cuda.synchronize()
+    out = s.cpu().numpy(), f.cpu().numpy()
+    gdb.close()
+    return out
+
+
+def _oracle(filt, emis, db, ids=None):
+    prof = oq.quantize(emis, synth.BG)
+    return oracle.score_db(filt, prof, db.res, db.offsets, ids=ids)
+
+
+def _assert_same(got, exp, ids=None, what=""):
+    gs, gf = got
+    es, ef = exp
+    if ids is not None:
+        gs, gf, es, ef = gs[ids], gf[ids], es[ids], ef[ids]
+    bad = np.nonzero((gs != es) | (gf != ef))[0]
+    assert bad.size == 0, (f"{what}: {bad.size} mismatches, first at {bad[:5]}: "
+                           f"gpu {gs[bad[:5]]}/{gf[bad[:5]]} oracle {es[bad[:5]]}/{ef[bad[:5]]}")
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    return synth.plain_msv_m48()
+
+
+@pytest.mark.parametrize("filt", ["msv", "ssv"])
+def test_m48_2k_default_plan(hm, cfg0, filt):
+    emis = cfg0.emissions[0]
+    print(f"case m48_2k {filt}", flush=True)
+    _assert_same(_gpu(hm, filt, emis, cfg0.db), _oracle(filt, emis, cfg0.db), what=filt)
+
+
+PLANS_M48 = [(4, 6), (4, 7), (8, 3), (8, 5), (16, 2), (32, 1), (64, 1)]
+
+
+@pytest.mark.parametrize("filt", ["msv", "ssv"])
+@pytest.mark.parametrize("gq", PLANS_M48, ids=lambda t: f"G{t[0]}Q{t[1]}")
+def test_m48_every_group_width(hm, cfg0, filt, gq):
+    emis = cfg0.emissions[0]
+    G, Q = gq
+    print(f"case m48 {filt} G={G} Q={Q}", flush=True)
+    plan = hm.make_plan(G, Q, waves_per_block=2, blocks=0, tile=8)
+    _assert_same(_gpu(hm, filt, emis, cfg0.db, plan), _oracle(filt, emis, cfg0.db),
+                 what=f"{filt} G{G} Q{Q}")
+
+
+def _implanted_db(rng, emis, n, lo, hi, frac):
+    db = synth.random_db(rng, n, lo, hi)
+    synth.implant(rng, db.res, db.offsets, [emis], frac)
+    return db
+
+
+@pytest.mark.parametrize("filt", ["msv", "ssv"])
+@pytest.mark.parametrize("M", [1, 2, 17, 100, 257, 400, 1000, 2400, 3840])
+def test_lengths_and_implants(hm, filt, M):
+    """Ragged lengths (0..700, some invalid codes), 10% implants from the
+    query so overflow and the J loop occur, across profile lengths."""
+    rng = np.random.default_rng(1000 + M)
+    emis = synth.sample_emissions(rng, M)
+    n = 600 if M < 1000 else 250
+    db = _implanted_db(rng, emis, n, 0, 700, 0.1)
+    db.res[rng.random(db.res.size) < 0.002] = rng.integers(20, 32)
+    print(f"case lengths {filt} M={M} n={n}", flush=True)
+    got = _gpu(hm, filt, emis, db)
+    exp = _oracle(filt, emis, db)
+    _assert_same(got, exp, what=f"{filt} M={M}")
+    if M >= (17 if filt == "msv" else 100):
+        assert exp[1].sum() > 0          # overflow path exercised
+
+
+@pytest.mark.parametrize("tile", [4, 8, 64, 256])
+def test_msv_tile_sizes_agree(hm, tile):
+    rng = np.random.default_rng(77)
+    emis = synth.sample_emissions(rng, 130)
+    db = _implanted_db(rng, emis, 800, 1, 400, 0.15)
+    print(f"case msv tile={tile}", flush=True)
+    plan = hm.make_plan(8, 9, waves_per_block=4, tile=tile)
+    _assert_same(_gpu(hm, "msv", emis, db, plan), _oracle("msv", emis, db), what=f"tile {tile}")
+
+
+@pytest.mark.parametrize("filt", ["msv", "ssv"])
+def test_edge_sequences(hm, filt):
+    """Empty, all-invalid, single-residue, long (5000) sequences and
+    single-sequence and sub-group-count databases."""
+    rng = np.random.default_rng(5)
+    emis = synth.sample_emissions(rng, 64)
+    seqs = [np.zeros(0, np.uint8), np.full(9, 20, np.uint8), np.full(3, 31, np.uint8),
+            np.array([3], np.uint8), rng.integers(0, 20, 5000).astype(np.uint8),
+            rng.integers(0, 20, 4).astype(np.uint8), rng.integers(0, 20, 5).astype(np.uint8)]
+    lens = np.array([len(s) for s in seqs])
+    off = np.zeros(len(seqs) + 1, np.int64)
+    off[1:] = np.cumsum(lens)
+    db = synth.Database(np.concatenate(seqs), off)
+    print(f"case edges {filt}", flush=True)
+    _assert_same(_gpu(hm, filt, emis, db), _oracle(filt, emis, db), what="edges")
+    one = db.subset([4])
+    _assert_same(_gpu(hm, filt, emis, one), _oracle(filt, emis, one), what="single")
+
+
+def test_repeated_calls_share_workspace(hm, cfg0):
+    emis = cfg0.emissions[0]
+    prof = hm.Profile.from_emissions(emis, synth.BG)
+    gdb = hm.Database(cfg0.db.res, cfg0.db.offsets)
+    ws = hm.new_workspace()
+    outs = []
+    for _ in range(3):
+        s, f = hm.msv_score(prof, gdb, workspace=ws)
+        outs.append((s.clone(), f.clone()))
+    torch.cuda.synchronize()
+    for s, f in outs[1:]:
+        assert torch.equal(s, outs[0][0]) and torch.equal(f, outs[0][1])
+    gdb.close()
