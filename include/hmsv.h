@@ -43,7 +43,7 @@ const char *hmsv_strerror(hmsv_status s);
 #define HMSV_KP       32    /* table rows: codes 20..31 are non-scoring (Alg. 4's 32-entry table) */
 #define HMSV_BASE    190    /* N/J level of the MSV special states */
 #define HMSV_TEC       3    /* E->J and E->C cost, -round(3 log2 1/2) */
-#define HMSV_MAX_M  3840    /* longest profile: the LDS table (21 x 3840 x 2 B) fits 160 KiB */
+#define HMSV_MAX_M  3839    /* longest profile: its LDS table (21 rows x 3840 fp16) fits 160 KiB */
 #define HMSV_MAX_BIAS 64    /* dbias bound under which the kernels may omit the 255 cap */
 
 /* Uniform local-entry cost of a length-M profile: -round(3 log2(2/(M(M+1)))),
@@ -106,8 +106,8 @@ int64_t hmsv_db_padded_rows(const hmsv_db *db);  /* rows the kernels run */
 
 /* ---- launch plan --------------------------------------------------------
  * How one filter call maps onto the GPU.  A lane group of G lanes (4..64)
- * aligns one sequence; each lane holds Q packed pairs of nodes, so the
- * group covers 2*G*Q >= M nodes.  64/G sequences share a wavefront (the
+ * aligns one sequence; each lane holds Q packed pairs of cells, so the
+ * group covers 2*G*Q - 1 >= M nodes (one cell is a fixed -inf node).  64/G sequences share a wavefront (the
  * paper's multi-sequence alignment, Sec. 3.1 tier 4).  waves_per_block
  * wavefronts share one LDS copy of the profile; blocks = 0 picks a
  * persistent grid of the resident maximum.  tile is the number of rows
@@ -123,7 +123,8 @@ typedef struct {
 /* The library's default plan for a filter ("msv" = 1, "ssv" = 0) and M. */
 hmsv_status hmsv_default_plan(int32_t is_msv, int32_t M, hmsv_plan *plan);
 
-/* Device workspace needed by a scoring call (bytes, small and fixed). */
+/* Device workspace needed by a scoring call (bytes, fixed: the work-queue
+ * counters plus the profile converted to the kernel's LDS layout). */
 size_t hmsv_workspace_bytes(void);
 
 /* ---- scoring -----------------------------------------------------------
@@ -132,9 +133,9 @@ size_t hmsv_workspace_bytes(void);
  * SSV (paper Alg. 7): score[i] = best single-segment score in signed 8-bit
  * (-128 = no positive segment), flags[i] = 1 on saturation (score = 127).
  * score, flags: device, [nseq] each, written for every sequence.
- * workspace: device, hmsv_workspace_bytes() bytes, caller-owned; its content
- * need not be initialised; calls that share a workspace must be ordered on
- * one stream.  plan: NULL for the default.  The call allocates nothing.
+ * workspace: device, hmsv_workspace_bytes() bytes, 256-byte aligned,
+ * caller-owned; its content need not be initialised; calls that share a
+ * workspace must be ordered on one stream.  plan: NULL for the default.  The call allocates nothing.
  * Fails with HMSV_EINVAL on null pointers or a profile outside its
  * preconditions, HMSV_ENOKERNEL if the plan was not instantiated,
  * HMSV_EDEVICE if the launch fails. */

@@ -30,7 +30,7 @@ K = 20
 KP = 32
 BASE = 190
 TEC = 3
-MAX_M = 3840
+MAX_M = 3839
 MAX_BIAS = 64
 
 

@@ -15,7 +15,6 @@ using namespace hmsv;
 
 namespace hmsv {
 int register_kernels(const KernelEntry *entries, int n);
-hipError_t launch_zero(uint32_t *p, int n, hipStream_t s);
 }
 
 struct hmsv_db {
@@ -54,10 +53,6 @@ Registry &registry() {
     return r;
 }
 
-__global__ void zero_kernel(uint32_t *p, int n) {
-    int i = threadIdx.x;
-    if (i < n) p[i] = 0u;
-}
 
 // Persistent-grid size per (kernel, waves_per_block), measured once per device.
 struct OccKey { const KernelEntry *e; int wpb; int dev; };
@@ -95,7 +90,7 @@ hmsv_status check_profile(const hmsv_profile *p, int is_msv) {
 hmsv_status check_plan(const hmsv_plan *pl, int M) {
     if (pl->G < 1 || pl->G > 64 || (64 % pl->G) != 0) return HMSV_EINVAL;
     if (pl->Q < 1) return HMSV_EINVAL;
-    if ((int64_t)2 * pl->G * pl->Q < M) return HMSV_EINVAL;
+    if (plan_nodes(pl->G, pl->Q) < M) return HMSV_EINVAL;
     if (pl->waves_per_block < 1 || pl->waves_per_block > 8) return HMSV_EINVAL;
     if (pl->blocks < 0) return HMSV_EINVAL;
     if (pl->tile < 4 || (pl->tile % 4) != 0) return HMSV_EINVAL;
@@ -136,6 +131,8 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
     a.score = score;
     a.flag = flags;
     a.counter = (uint32_t *)workspace;
+    a.image = (uint32_t *)((char *)workspace + kWsCounterBytes);
+    if (((uintptr_t)workspace & 255u) != 0) return HMSV_EINVAL;
 
     int blocks = plan.blocks;
     if (blocks == 0) {
@@ -146,7 +143,6 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
         int64_t need = (db->nseq + groups_per_block - 1) / groups_per_block;
         if (need < blocks) blocks = (int)need;
     }
-    if (launch_zero(a.counter, 4, stream) != hipSuccess) return HMSV_EDEVICE;
     if (e->launch(a, plan.waves_per_block, blocks, stream) != hipSuccess) return HMSV_EDEVICE;
     return HMSV_OK;
 }
@@ -159,10 +155,6 @@ int register_kernels(const KernelEntry *entries, int n) {
     return n;
 }
 
-hipError_t launch_zero(uint32_t *p, int n, hipStream_t s) {
-    hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, p, n);
-    return hipGetLastError();
-}
 }  // namespace hmsv
 
 extern "C" {
@@ -305,31 +297,25 @@ hmsv_status hmsv_default_plan(int32_t is_msv, int32_t M, hmsv_plan *plan) {
     if (!plan) return HMSV_EINVAL;
     if (M < 1) return HMSV_EINVAL;
     if (M > HMSV_MAX_M) return HMSV_EUNSUPPORTED;
-    // Lane-ops per cell ~ G * (ops_per_pair * Q + per_row) / M: pick the
-    // group width that minimises it among instantiated kernels.
-    const double per_pair = is_msv ? 3.0 : 2.0;
-    const double per_row = 8.0;
-    double best = 1e30;
-    hmsv_plan bp{};
+    // Narrowest lane group whose registers (Q <= 32 per lane) still hold the
+    // profile: more sequences per wavefront and more cells per row of
+    // per-row overhead (measured best at M = 48, 400 and 2400).
     for (int G : {4, 8, 16, 32, 64}) {
-        int Q = (M + 2 * G - 1) / (2 * G);
+        int Q = (M + 1 + 2 * G - 1) / (2 * G);
+        if (Q > 32 || lds_bytes(G, Q) > (size_t)kLdsBytes) continue;
         if (!registry().find(is_msv, G, Q)) continue;
-        double cost = G * (per_pair * Q + per_row);
-        if (cost < best) {
-            best = cost;
-            bp.G = G;
-            bp.Q = Q;
-        }
+        plan->G = G;
+        plan->Q = Q;
+        // large tables allow one block per CU: fill it with wavefronts
+        plan->waves_per_block = lds_bytes(G, Q) > 48 * 1024 ? 8 : 4;
+        plan->blocks = 0;
+        plan->tile = 64;
+        return HMSV_OK;
     }
-    if (best >= 1e30) return HMSV_ENOKERNEL;
-    bp.waves_per_block = 4;
-    bp.blocks = 0;
-    bp.tile = 32;
-    *plan = bp;
-    return HMSV_OK;
+    return HMSV_ENOKERNEL;
 }
 
-size_t hmsv_workspace_bytes(void) { return 256; }
+size_t hmsv_workspace_bytes(void) { return kWsBytes; }
 
 hmsv_status hmsv_msv_score(const hmsv_profile *prof, const hmsv_db *db, uint8_t *score,
                            uint8_t *flags, void *workspace, const hmsv_plan *plan,

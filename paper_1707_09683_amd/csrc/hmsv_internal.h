@@ -34,8 +34,13 @@ struct KArgs {
     uint32_t pad_off;      // offset of >= 16 non-scoring residues
     uint8_t *score;
     uint8_t *flag;
-    uint32_t *counter;     // work-queue head, zero at launch
+    uint32_t *counter;     // work-queue head, zeroed by the prep kernel
+    uint32_t *image;       // LDS image of the profile (workspace), 16-byte aligned
 };
+
+// Workspace layout: queue counters, then the profile's LDS image.
+constexpr size_t kWsCounterBytes = 256;
+constexpr size_t kWsBytes = kWsCounterBytes + 160 * 1024;
 
 typedef hipError_t (*LaunchFn)(const KArgs &, int waves_per_block, int blocks,
                                hipStream_t);
@@ -49,11 +54,19 @@ struct KernelEntry {
     OccupancyFn occupancy;
 };
 
-inline size_t lds_bytes(int G, int Q) { return (size_t)kRows * G * Q * 4; }
+// LDS read width per lane (dwords) and the table's padded register count.
+inline int read_width_host(int G) { return G >= 32 ? 1 : (G >= 16 ? 2 : 4); }
+inline size_t lds_bytes(int G, int Q) {
+    int W = read_width_host(G);
+    int qp = (Q + W - 1) / W * W;
+    return (size_t)kRows * G * qp * 4;
+}
+// A group of G lanes with Q registers covers nodes 1..2GQ-1 (slot 0 is a
+// dummy -inf node).
+inline int64_t plan_nodes(int G, int Q) { return (int64_t)2 * G * Q - 1; }
 
 // Each kernel translation unit registers its instantiations at load time.
 int register_kernels(const KernelEntry *entries, int n);
 
-hipError_t launch_zero(uint32_t *p, int n, hipStream_t s);
 
 }  // namespace hmsv

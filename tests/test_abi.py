@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_constants_match_oracle():
-    for M in (1, 2, 3, 48, 100, 400, 1000, 2400, 3840):
+    for M in (1, 2, 3, 48, 100, 400, 1000, 2400, 3839):
         assert hm.tbm(M) == oq.tbm(M)
     for L in (0, 1, 2, 3, 20, 21, 45, 350, 1000, 35000, 10 ** 6):
         assert hm.tjb(L) == oq.tjb(L)
@@ -45,7 +45,7 @@ def test_constants_match_oracle():
 
 def test_quantizer_matches_oracle_bit_for_bit():
     rng = np.random.default_rng(31)
-    for M in (1, 7, 48, 400, 1000, 2400, 3840):
+    for M in (1, 7, 48, 400, 1000, 2400, 3839):
         e = synth.sample_emissions(rng, M)
         a = hm.quantize(e, synth.BG)
         b = oq.quantize(e, synth.BG)
@@ -65,7 +65,7 @@ def test_quantizer_rejects_bad_input():
     with pytest.raises(hm.HmsvError):
         hm.quantize(bad, synth.BG)
     with pytest.raises(hm.HmsvError):
-        hm.quantize(np.full((3841, 20), 0.05), synth.BG)
+        hm.quantize(np.full((3840, 20), 0.05), synth.BG)
 
 
 def test_db_create_validates_on_host():
@@ -97,7 +97,7 @@ def test_score_rejects_bad_arguments_before_launch():
     assert hm._lib.hmsv_ssv_score(ctypes.byref(prof), ctypes.c_void_p(1), 1, 1, ws, None,
                                   None) == -1
     prof = hm._CProfile(100, 10, 1, 1)
-    bad_plan = hm.make_plan(8, 2)                 # covers 32 < 100 nodes
+    bad_plan = hm.make_plan(8, 2)                 # covers 31 < 100 nodes
     assert hm._lib.hmsv_msv_score(ctypes.byref(prof), ctypes.c_void_p(1), 1, 1, ws,
                                   ctypes.byref(bad_plan), None) == -1
     odd_plan = hm.make_plan(8, 7, tile=6)         # tile not a multiple of 4
@@ -108,8 +108,8 @@ def test_score_rejects_bad_arguments_before_launch():
 
 def test_default_plans_cover_every_length():
     for filt in ("msv", "ssv"):
-        for M in list(range(1, 200)) + list(range(200, 3841, 37)) + [3840]:
+        for M in list(range(1, 200)) + list(range(200, 3840, 37)) + [3839]:
             p = hm.default_plan(filt, M)
-            assert 2 * p.G * p.Q >= M and 64 % p.G == 0
+            assert 2 * p.G * p.Q - 1 >= M and 64 % p.G == 0
     with pytest.raises(hm.HmsvError):
-        hm.default_plan("msv", 3841)
+        hm.default_plan("msv", 3840)

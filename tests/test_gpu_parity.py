@@ -59,7 +59,7 @@ def test_m48_2k_default_plan(hm, cfg0, filt):
     _assert_same(_gpu(hm, filt, emis, cfg0.db), _oracle(filt, emis, cfg0.db), what=filt)
 
 
-PLANS_M48 = [(4, 6), (4, 7), (8, 3), (8, 5), (16, 2), (32, 1), (64, 1)]
+PLANS_M48 = [(4, 7), (4, 8), (8, 4), (8, 5), (16, 2), (32, 1), (64, 1)]
 
 
 @pytest.mark.parametrize("filt", ["msv", "ssv"])
@@ -80,7 +80,7 @@ def _implanted_db(rng, emis, n, lo, hi, frac):
 
 
 @pytest.mark.parametrize("filt", ["msv", "ssv"])
-@pytest.mark.parametrize("M", [1, 2, 17, 100, 257, 400, 1000, 2400, 3840])
+@pytest.mark.parametrize("M", [1, 2, 17, 100, 257, 400, 1000, 2400, 3839])
 def test_lengths_and_implants(hm, filt, M):
     """Ragged lengths (0..700, some invalid codes), 10% implants from the
     query so overflow and the J loop occur, across profile lengths."""
