@@ -146,6 +146,57 @@ hmsv_status hmsv_ssv_score(const hmsv_profile *prof, const hmsv_db *db,
                            int8_t *score, uint8_t *flags, void *workspace,
                            const hmsv_plan *plan, hipStream_t stream);
 
+/* ---- partial scoring (serving) -------------------------------------------
+ * As hmsv_msv_score / hmsv_ssv_score, but only for the sequences at
+ * positions [first, first + count) of the database's processing order
+ * (longest first, see hmsv_db_order); results land at their original
+ * indices and other entries of score/flags are left untouched.  Lets a
+ * server split one search into chunks and interleave the chunks of
+ * several searches.  Fails with HMSV_EINVAL if the range is outside
+ * [0, nseq]. */
+hmsv_status hmsv_msv_score_range(const hmsv_profile *prof, const hmsv_db *db, int64_t first,
+                                 int64_t count, uint8_t *score, uint8_t *flags,
+                                 void *workspace, const hmsv_plan *plan, hipStream_t stream);
+hmsv_status hmsv_ssv_score_range(const hmsv_profile *prof, const hmsv_db *db, int64_t first,
+                                 int64_t count, int8_t *score, uint8_t *flags,
+                                 void *workspace, const hmsv_plan *plan, hipStream_t stream);
+
+/* Processing order of a packed database: ids[t] = original index of the
+ * t-th sequence (longest first; ties keep the original order).
+ * ids: host, [nseq] int64 out. */
+hmsv_status hmsv_db_order(const hmsv_db *db, int64_t *ids);
+
+/* ---- batched launches ---------------------------------------------------
+ * Many queries (profiles of any length, MSV or SSV) against one database in
+ * a single graph launch.  hmsv_batch_create captures, for every query, the
+ * prep and filter kernels of its plan into one hipGraph whose queries are
+ * spread over `branches` independent branches (longest profiles first,
+ * balanced by M), so their persistent kernels can overlap on the device;
+ * hmsv_batch_launch replays the whole batch with one hipGraphLaunch.
+ * Every query's results are identical to its plain hmsv_*_score call with
+ * the same plan.
+ * Each query owns its outputs and workspace (device, caller-owned, distinct
+ * per query); score is uint8 for MSV, int8 for SSV.  plan.G == 0 selects
+ * the library's default plan.  The batch keeps pointers, not copies, of
+ * the device buffers; the profile struct is copied.  branches: 1..16.
+ * Fails with HMSV_EINVAL on bad arguments (including a workspace shared by
+ * two queries), the errors of hmsv_*_score for a query, HMSV_EDEVICE if
+ * capture or instantiation fails. */
+typedef struct {
+    int32_t is_msv;
+    hmsv_profile prof;
+    void *score;        /* device, [nseq] */
+    uint8_t *flags;     /* device, [nseq] */
+    void *workspace;    /* device, hmsv_workspace_bytes() */
+    hmsv_plan plan;     /* plan.G == 0: default */
+} hmsv_query;
+
+typedef struct hmsv_batch hmsv_batch;
+hmsv_status hmsv_batch_create(const hmsv_query *queries, int32_t nq, const hmsv_db *db,
+                              int32_t branches, hmsv_batch **out);
+hmsv_status hmsv_batch_launch(hmsv_batch *batch, hipStream_t stream);
+void hmsv_batch_destroy(hmsv_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -86,10 +86,18 @@ for _f in ("hmsv_msv_score", "hmsv_ssv_score"):
     getattr(_lib, _f).restype = ctypes.c_int
     getattr(_lib, _f).argtypes = [ctypes.POINTER(_CProfile), _P, _P, _P, _P,
                                   ctypes.POINTER(Plan), _P]
+for _f in ("hmsv_msv_score_range", "hmsv_ssv_score_range"):
+    getattr(_lib, _f).restype = ctypes.c_int
+    getattr(_lib, _f).argtypes = [ctypes.POINTER(_CProfile), _P, _i64, _i64, _P, _P, _P,
+                                  ctypes.POINTER(Plan), _P]
+_lib.hmsv_db_order.restype = ctypes.c_int
+_lib.hmsv_db_order.argtypes = [_P, _P]
 
 EXPORTED = ("hmsv_strerror", "hmsv_tbm", "hmsv_tjb", "hmsv_quantize", "hmsv_db_create",
             "hmsv_db_destroy", "hmsv_db_nseq", "hmsv_db_residues", "hmsv_db_padded_rows",
-            "hmsv_default_plan", "hmsv_workspace_bytes", "hmsv_msv_score", "hmsv_ssv_score")
+            "hmsv_default_plan", "hmsv_workspace_bytes", "hmsv_msv_score", "hmsv_ssv_score",
+            "hmsv_batch_create", "hmsv_batch_launch", "hmsv_batch_destroy",
+            "hmsv_msv_score_range", "hmsv_ssv_score_range", "hmsv_db_order")
 
 
 def _check(rc: int, what: str):
@@ -161,9 +169,16 @@ class Database:
             _check(_lib.hmsv_db_create(_np_ptr(res) if res.size else None, _np_ptr(off),
                                        len(off) - 1, ctypes.byref(h)), "hmsv_db_create")
         self._h = h
+        self.lengths = np.diff(off)
         self.nseq = int(_lib.hmsv_db_nseq(h))
         self.residues = int(_lib.hmsv_db_residues(h))
         self.padded_rows = int(_lib.hmsv_db_padded_rows(h))
+
+    def order(self) -> np.ndarray:
+        """Processing order: original index of each position (longest first)."""
+        ids = np.empty(self.nseq, np.int64)
+        _check(_lib.hmsv_db_order(self._h, _np_ptr(ids)), "hmsv_db_order")
+        return ids
 
     def close(self):
         if getattr(self, "_h", None):
@@ -184,8 +199,25 @@ def default_plan(filt: str, M: int) -> Plan:
     return p
 
 
-def make_plan(G, Q, waves_per_block=4, blocks=0, tile=32) -> Plan:
+def make_plan(G, Q, waves_per_block=4, blocks=0, tile=64) -> Plan:
     return Plan(int(G), int(Q), int(waves_per_block), int(blocks), int(tile))
+
+
+_tuned = None
+
+
+def plan_for(filt: str, M: int) -> Plan:
+    """The autotuned plan for this device (tuned_plans.json, nearest M-bin),
+    or the library's default plan when no tuned entry applies."""
+    global _tuned
+    from . import autotune
+    if _tuned is None:
+        table = autotune.load_table()
+        key = autotune.device_key() if table and torch.cuda.is_available() else None
+        _tuned = (table, key)
+    table, key = _tuned
+    t = autotune.lookup(table, key, filt, int(M)) if key else None
+    return make_plan(*t) if t else default_plan(filt, M)
 
 
 def workspace_bytes() -> int:
@@ -196,7 +228,8 @@ def new_workspace(device="cuda") -> torch.Tensor:
     return torch.zeros(workspace_bytes(), dtype=torch.uint8, device=device)
 
 
-def _score(filt, profile: Profile, db: Database, score, flags, workspace, plan, stream):
+def _score(filt, profile: Profile, db: Database, score, flags, workspace, plan, stream,
+           rng=None):
     dev = profile.device
     n = db.nseq
     sdt = torch.uint8 if filt == "msv" else torch.int8
@@ -218,11 +251,20 @@ def _score(filt, profile: Profile, db: Database, score, flags, workspace, plan, 
             raise ValueError("all tensors must be on the profile's device")
     if stream is None:
         stream = torch.cuda.current_stream(dev)
-    fn = _lib.hmsv_msv_score if filt == "msv" else _lib.hmsv_ssv_score
+    if plan is None:
+        plan = plan_for(filt, profile.M)
+    pl = ctypes.byref(plan) if plan is not None else None
     with torch.cuda.device(dev):
-        _check(fn(ctypes.byref(profile._c), db._h, score.data_ptr(), flags.data_ptr(),
-                  workspace.data_ptr(), ctypes.byref(plan) if plan is not None else None,
-                  ctypes.c_void_p(stream.cuda_stream)), f"hmsv_{filt}_score")
+        if rng is None:
+            fn = _lib.hmsv_msv_score if filt == "msv" else _lib.hmsv_ssv_score
+            _check(fn(ctypes.byref(profile._c), db._h, score.data_ptr(), flags.data_ptr(),
+                      workspace.data_ptr(), pl, ctypes.c_void_p(stream.cuda_stream)),
+                   f"hmsv_{filt}_score")
+        else:
+            fn = _lib.hmsv_msv_score_range if filt == "msv" else _lib.hmsv_ssv_score_range
+            _check(fn(ctypes.byref(profile._c), db._h, int(rng[0]), int(rng[1]),
+                      score.data_ptr(), flags.data_ptr(), workspace.data_ptr(), pl,
+                      ctypes.c_void_p(stream.cuda_stream)), f"hmsv_{filt}_score_range")
     return score, flags
 
 
@@ -234,3 +276,10 @@ def msv_score(profile, db, score=None, flags=None, workspace=None, plan=None, st
 def ssv_score(profile, db, score=None, flags=None, workspace=None, plan=None, stream=None):
     """SSV filter (paper Alg. 7): int8 scores and overflow flags per sequence."""
     return _score("ssv", profile, db, score, flags, workspace, plan, stream)
+
+
+def score_range(filt, profile, db, first, count, score, flags, workspace=None, plan=None,
+                stream=None):
+    """Score positions [first, first+count) of the processing order (see
+    Database.order) into the full-size score/flags tensors."""
+    return _score(filt, profile, db, score, flags, workspace, plan, stream, (first, count))

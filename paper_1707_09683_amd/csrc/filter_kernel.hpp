@@ -17,8 +17,8 @@
 //    and maxima are exact, the clamp modifier's floor at 0.0 is the 8-bit
 //    floor (-inf), and its cap at 1.0 is never reached before the overflow
 //    row.  A cell update is then
-//      MSV  v = clamp(max(gamma, scB) + (dbias - cost)/1024)   (Alg. 2 lines 17-19)
-//      SSV  v = clamp(gamma + sc/1024)                          (Alg. 7 lines 16-17)
+//      MSV  v = clamp(max(gamma, scB) + (dbias - cost)/1024)   (Alg. 2 cell update)
+//      SSV  v = clamp(gamma + sc/1024)                          (Alg. 7 cell update)
 //    and scE = max(scE, v, v') takes two cells per v_pk_maximum3_f16
 //    (a running max, never reset per row).  The 255 (MSV) / 127 (SSV) caps
 //    are not applied; overflow is flagged from the running max instead,
@@ -33,7 +33,7 @@
 //    max(base + tec, the max it was last computed from), so rows run in
 //    tiles with scB fixed; at the tile end the group max is checked and, if
 //    it moved (or overflowed), the tile is replayed from a register
-//    checkpoint with the per-row special-state update (Alg. 2 lines 24-25).
+//    checkpoint with the per-row special-state update of Alg. 2.
 #pragma once
 #include "hmsv_internal.h"
 
@@ -167,7 +167,7 @@ struct Lane {
         }
     }
 
-    // One residue row: Alg. 2 lines 13-23 (MSV) / Alg. 7 lines 12-20 (SSV).
+    // One residue row of Alg. 2 (MSV) / Alg. 7 (SSV): shift, fetch, cell update.
     __device__ __forceinline__ void row(const uint32_t *T, uint32_t x) {
         uint32_t c[Q];
         load_row(T, x, c);
@@ -310,7 +310,7 @@ filter_kernel(KArgs a) {
             }
         }
 
-        // ---- finished sequences: record scores (Alg. 2 lines 27-31) -----
+        // ---- finished sequences: record scores (Alg. 2 end-residue branch) -----
         if (__any(ended)) {
             int mx = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
             if (ended && gstart) {

@@ -17,6 +17,12 @@ namespace hmsv {
 int register_kernels(const KernelEntry *entries, int n);
 }
 
+struct hmsv_batch {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int nq = 0;
+};
+
 struct hmsv_db {
     int64_t nseq = 0;
     int64_t residues = 0;
@@ -25,6 +31,7 @@ struct hmsv_db {
     SeqRec *d_seqs = nullptr;
     uint32_t pad_off = 0;
     int device = 0;
+    std::vector<int64_t> order;   // processing order -> original index
 };
 
 namespace {
@@ -99,6 +106,7 @@ hmsv_status check_plan(const hmsv_plan *pl, int M) {
 }
 
 hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db,
+                         int64_t first, int64_t count,
                          uint8_t *score, uint8_t *flags, void *workspace,
                          const hmsv_plan *plan_in, hipStream_t stream) {
     hmsv_status st = check_profile(prof, is_msv);
@@ -115,7 +123,9 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
     if (st != HMSV_OK) return st;
     const KernelEntry *e = registry().find(is_msv, plan.G, plan.Q);
     if (!e) return HMSV_ENOKERNEL;
-    if (db->nseq == 0) return HMSV_OK;
+    if (count == -1 && first == 0) count = db->nseq;      // whole database
+    if (first < 0 || count < 0 || first > db->nseq || count > db->nseq - first) return HMSV_EINVAL;
+    if (count == 0) return HMSV_OK;
 
     KArgs a;
     a.cost = prof->cost;
@@ -125,8 +135,8 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
     a.tbm = hmsv_tbm(prof->M);
     a.tile_blocks = plan.tile / 4;
     a.res = db->d_res;
-    a.seqs = db->d_seqs;
-    a.nseq = (int32_t)db->nseq;
+    a.seqs = db->d_seqs + first;
+    a.nseq = (int32_t)count;
     a.pad_off = db->pad_off;
     a.score = score;
     a.flag = flags;
@@ -140,7 +150,7 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
         if (blocks <= 0) return HMSV_EDEVICE;
         // no more wavefronts than there are lane groups' worth of sequences
         int64_t groups_per_block = (int64_t)plan.waves_per_block * (64 / plan.G);
-        int64_t need = (db->nseq + groups_per_block - 1) / groups_per_block;
+        int64_t need = (count + groups_per_block - 1) / groups_per_block;
         if (need < blocks) blocks = (int)need;
     }
     if (e->launch(a, plan.waves_per_block, blocks, stream) != hipSuccess) return HMSV_EDEVICE;
@@ -246,6 +256,7 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
         recs[t].rows = (uint32_t)r;
         recs[t].id = (uint32_t)i;
         recs[t].tjb = (uint32_t)hmsv_tjb(len[i]);
+
         total += r;
         rows += r;
         if (total >= ((uint64_t)1 << 32) - 64) return HMSV_EUNSUPPORTED;
@@ -265,6 +276,12 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
     db->residues = residues;
     db->rows = (int64_t)rows;
     db->pad_off = pad_off;
+    try {
+        db->order = order;
+    } catch (...) {
+        delete db;
+        return HMSV_ENOMEM;
+    }
     if (hipGetDevice(&db->device) != hipSuccess) { delete db; return HMSV_EDEVICE; }
     if (hipMalloc(&db->d_res, bytes) != hipSuccess) { delete db; return HMSV_ENOMEM; }
     if (hipMalloc(&db->d_seqs, sizeof(SeqRec) * (size_t)std::max<int64_t>(1, nseq)) != hipSuccess) {
@@ -320,13 +337,145 @@ size_t hmsv_workspace_bytes(void) { return kWsBytes; }
 hmsv_status hmsv_msv_score(const hmsv_profile *prof, const hmsv_db *db, uint8_t *score,
                            uint8_t *flags, void *workspace, const hmsv_plan *plan,
                            hipStream_t stream) {
-    return score_common(1, prof, db, score, flags, workspace, plan, stream);
+    return score_common(1, prof, db, 0, -1, score, flags, workspace, plan, stream);
 }
 
 hmsv_status hmsv_ssv_score(const hmsv_profile *prof, const hmsv_db *db, int8_t *score,
                            uint8_t *flags, void *workspace, const hmsv_plan *plan,
                            hipStream_t stream) {
-    return score_common(0, prof, db, (uint8_t *)score, flags, workspace, plan, stream);
+    return score_common(0, prof, db, 0, -1, (uint8_t *)score, flags, workspace, plan, stream);
+}
+
+hmsv_status hmsv_msv_score_range(const hmsv_profile *prof, const hmsv_db *db, int64_t first,
+                                 int64_t count, uint8_t *score, uint8_t *flags,
+                                 void *workspace, const hmsv_plan *plan, hipStream_t stream) {
+    if (count < 0) return HMSV_EINVAL;
+    return score_common(1, prof, db, first, count, score, flags, workspace, plan, stream);
+}
+
+hmsv_status hmsv_ssv_score_range(const hmsv_profile *prof, const hmsv_db *db, int64_t first,
+                                 int64_t count, int8_t *score, uint8_t *flags,
+                                 void *workspace, const hmsv_plan *plan, hipStream_t stream) {
+    if (count < 0) return HMSV_EINVAL;
+    return score_common(0, prof, db, first, count, (uint8_t *)score, flags, workspace, plan,
+                        stream);
+}
+
+hmsv_status hmsv_db_order(const hmsv_db *db, int64_t *ids) {
+    if (!db || (!ids && db->nseq > 0)) return HMSV_EINVAL;
+    if (db->nseq > 0) std::memcpy(ids, db->order.data(), sizeof(int64_t) * (size_t)db->nseq);
+    return HMSV_OK;
+}
+
+hmsv_status hmsv_batch_create(const hmsv_query *queries, int32_t nq, const hmsv_db *db,
+                              int32_t branches, hmsv_batch **out) {
+    if (!out || !queries || !db || nq < 1 || branches < 1 || branches > 16) return HMSV_EINVAL;
+    *out = nullptr;
+    // validate everything before any capture starts
+    std::vector<hmsv_plan> plans((size_t)nq);
+    for (int i = 0; i < nq; ++i) {
+        const hmsv_query &q = queries[i];
+        hmsv_status st = check_profile(&q.prof, q.is_msv ? 1 : 0);
+        if (st != HMSV_OK) return st;
+        if (!q.score || !q.flags || !q.workspace) return HMSV_EINVAL;
+        if (((uintptr_t)q.workspace & 255u) != 0) return HMSV_EINVAL;
+        for (int k = 0; k < i; ++k)
+            if (queries[k].workspace == q.workspace) return HMSV_EINVAL;
+        if (q.plan.G == 0) {
+            st = hmsv_default_plan(q.is_msv ? 1 : 0, q.prof.M, &plans[i]);
+            if (st != HMSV_OK) return st;
+        } else {
+            plans[i] = q.plan;
+        }
+        st = check_plan(&plans[i], q.prof.M);
+        if (st != HMSV_OK) return st;
+        if (!registry().find(q.is_msv ? 1 : 0, plans[i].G, plans[i].Q)) return HMSV_ENOKERNEL;
+    }
+    // longest profiles first, each onto the branch with the least work so far
+    std::vector<int> order((size_t)nq);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return queries[a].prof.M > queries[b].prof.M; });
+    std::vector<int64_t> load((size_t)branches, 0);
+    std::vector<int> branch_of((size_t)nq);
+    for (int i : order) {
+        int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        branch_of[i] = b;
+        load[b] += queries[i].prof.M;
+    }
+    std::vector<hipStream_t> st((size_t)branches, nullptr);
+    std::vector<hipEvent_t> ev((size_t)branches + 1, nullptr);
+    hmsv_status rc = HMSV_OK;
+    hipGraph_t graph = nullptr;
+    bool capturing = false;
+    for (int b = 0; b < branches && rc == HMSV_OK; ++b)
+        if (hipStreamCreateWithFlags(&st[b], hipStreamNonBlocking) != hipSuccess) rc = HMSV_EDEVICE;
+    for (auto &e : ev)
+        if (rc == HMSV_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            rc = HMSV_EDEVICE;
+    if (rc == HMSV_OK) {
+        if (hipStreamBeginCapture(st[0], hipStreamCaptureModeRelaxed) != hipSuccess) rc = HMSV_EDEVICE;
+        else capturing = true;
+    }
+    if (rc == HMSV_OK) {
+        // fork: every branch starts after the capture origin
+        if (hipEventRecord(ev[branches], st[0]) != hipSuccess) rc = HMSV_EDEVICE;
+        for (int b = 1; b < branches && rc == HMSV_OK; ++b)
+            if (hipStreamWaitEvent(st[b], ev[branches], 0) != hipSuccess) rc = HMSV_EDEVICE;
+    }
+    for (int i : order) {
+        if (rc != HMSV_OK) break;
+        const hmsv_query &q = queries[i];
+        rc = score_common(q.is_msv ? 1 : 0, &q.prof, db, 0, db->nseq, (uint8_t *)q.score,
+                          q.flags, q.workspace, &plans[i], st[branch_of[i]]);
+    }
+    if (rc == HMSV_OK) {
+        // join every branch back into the origin stream
+        for (int b = 1; b < branches && rc == HMSV_OK; ++b) {
+            if (hipEventRecord(ev[b], st[b]) != hipSuccess ||
+                hipStreamWaitEvent(st[0], ev[b], 0) != hipSuccess)
+                rc = HMSV_EDEVICE;
+        }
+    }
+    if (capturing) {
+        if (hipStreamEndCapture(st[0], &graph) != hipSuccess && rc == HMSV_OK) rc = HMSV_EDEVICE;
+    }
+    hmsv_batch *bt = nullptr;
+    if (rc == HMSV_OK) {
+        bt = new (std::nothrow) hmsv_batch;
+        if (!bt) rc = HMSV_ENOMEM;
+    }
+    if (rc == HMSV_OK) {
+        bt->graph = graph;
+        bt->nq = nq;
+        if (hipGraphInstantiate(&bt->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            rc = HMSV_EDEVICE;
+            bt->graph = nullptr;
+            delete bt;
+            bt = nullptr;
+        } else {
+            graph = nullptr;
+        }
+    }
+    if (graph) hipGraphDestroy(graph);
+    for (auto e : ev)
+        if (e) hipEventDestroy(e);
+    for (auto s2 : st)
+        if (s2) hipStreamDestroy(s2);
+    if (rc == HMSV_OK) *out = bt;
+    return rc;
+}
+
+hmsv_status hmsv_batch_launch(hmsv_batch *batch, hipStream_t stream) {
+    if (!batch || !batch->exec) return HMSV_EINVAL;
+    return hipGraphLaunch(batch->exec, stream) == hipSuccess ? HMSV_OK : HMSV_EDEVICE;
+}
+
+void hmsv_batch_destroy(hmsv_batch *batch) {
+    if (!batch) return;
+    if (batch->exec) hipGraphExecDestroy(batch->exec);
+    if (batch->graph) hipGraphDestroy(batch->graph);
+    delete batch;
 }
 
 }  // extern "C"

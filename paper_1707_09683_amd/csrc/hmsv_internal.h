@@ -29,8 +29,8 @@ struct KArgs {
     int32_t tbm;
     int32_t tile_blocks;   // rows per special-state check / 4
     const uint8_t *res;    // packed residues
-    const SeqRec *seqs;
-    int32_t nseq;
+    const SeqRec *seqs;    // already offset to the first record of the range
+    int32_t nseq;          // records in the range
     uint32_t pad_off;      // offset of >= 16 non-scoring residues
     uint8_t *score;
     uint8_t *flag;
