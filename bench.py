@@ -1,17 +1,28 @@
 #!/usr/bin/env python3
-"""Throughput of the MSV filter at M = 400 on one MI355X.
+"""Throughput of the MSV/SSV filters on one MI355X, plus batched and served forms.
 
-Workload: one M=400 profile (Dirichlet(0.5*bg) emissions) against 500,000
-synthetic protein sequences (lognormal lengths, mean ~350, clipped to
-20..35000, residues i.i.d. from the background, 1% carrying a segment
-emitted by the profile), seed 2.  A step is one full MSV pass of the
-profile over the database: the work-queue reset plus the filter kernel,
-with the packed database and profile already resident in HBM.
+Headline workload (value): the MSV filter of one M=400 profile
+(Dirichlet(0.5*bg) emissions) against 500,000 synthetic protein sequences
+(lognormal lengths, mean ~350, clipped to 20..35000, residues i.i.d. from
+the background, 1% carrying a segment emitted by the profile), seed 2.  A
+step is one full MSV pass of the profile over the database (the prep kernel
+that builds the profile's LDS image and the filter kernel), with the packed
+database already resident in HBM.  GCUPS = M x real residues / step time.
 
-Prints one JSON line: GCUPS (model nodes x real residues / s), the ALU
-roofline of the filter kernel (HIP events on its own stream), and the CPU
-oracle's throughput on the machine's host cores.  Every output of the timed
-runs is compared with the oracle (bit-exact) before the line is printed.
+The same line also reports:
+* ssv_m400: the SSV filter of an M=400 profile (seed 3) on the same database;
+* batched: 64 profiles with M ~ U{30..2400}, MSV/SSV alternating, against a
+  1,000,000-sequence lognormal database (seed 4), one hipGraph launch vs 64
+  sequential plain launches with the same plans (outputs must be identical;
+  a sample of sequences per query is checked against the oracle);
+* served: a resident 2,000,000-sequence database (seed 5) and a Poisson
+  stream of searches (M ~ U{30..2000}, MSV or SSV), replayed through the
+  continuous-batching server and through the plain one-request-per-launch
+  FIFO path; QPS = 0.7 x the plain path's measured capacity; p50/p99
+  latency (arrival -> results in host memory) and GCUPS for both.
+
+Every output of the timed headline runs is compared bit for bit with the
+CPU oracle, which is also timed on the host cores (cpu_baseline).
 """
 from __future__ import annotations
 
@@ -35,7 +46,11 @@ sys.path.insert(0, ROOT)
 CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
 PEAK_INSTR = CUS * LANES * CLOCK_HZ              # 39.3e12 lane-instructions/s
 INSTR_PER_CELL = {"msv": 1.25, "ssv": 0.75}
-PAPER_OPS_PER_CELL = {"msv": 4, "ssv": 2}        # 8-bit SIMD ops per cell in the K40 listings
+
+# HBM bytes per dispatch of the headline kernel (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, scaled by a 1 GiB device copy measured the same way; see
+# profiles/).  None until taken on the current kernel build.
+TRAFFIC_BYTES = None
 
 
 def parse():
@@ -47,9 +62,14 @@ def parse():
     ap.add_argument("--filter", choices=["msv", "ssv"], default="msv")
     ap.add_argument("--M", type=int, default=400)
     ap.add_argument("--plan", type=str, default="",
-                    help="G,Q,waves_per_block,blocks,tile (default: library's choice)")
+                    help="G,Q,waves_per_block,blocks,tile (default: tuned plan)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="headline only (no SSV, batched or served legs)")
+    ap.add_argument("--batch-nseq", type=int, default=1_000_000)
+    ap.add_argument("--serve-nseq", type=int, default=2_000_000)
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -68,6 +88,180 @@ def calibrate_copy(mib: int):
     print(json.dumps({"copy_bytes": n, "read_bytes": n, "write_bytes": n}))
 
 
+def nthreads(a):
+    return a.cpu_threads or max(1, min(16, os.cpu_count() or 1))
+
+
+def time_plain(hm, torch, filt, prof, gdb, plan, steps, warmup):
+    """Mean wall time per step (back-to-back) and mean HIP-event time per step."""
+    dev = prof.device
+    fn = hm.msv_score if filt == "msv" else hm.ssv_score
+    sdt = torch.uint8 if filt == "msv" else torch.int8
+    score = torch.empty(gdb.nseq, dtype=sdt, device=dev)
+    flags = torch.empty(gdb.nseq, dtype=torch.uint8, device=dev)
+    ws = hm.new_workspace(dev)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(warmup):
+        fn(prof, gdb, score, flags, ws, plan, stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t1 = time.perf_counter()
+    for s, e in ev:
+        s.record(stream)
+        fn(prof, gdb, score, flags, ws, plan, stream)
+        e.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t1) / steps
+    kern = float(np.mean([s.elapsed_time(e) for s, e in ev])) * 1e-3
+    return wall, kern, score, flags
+
+
+def headline(a, hm, torch, synth):
+    t0 = time.time()
+    w = synth.plain_msv_m400(nseq=a.nseq)
+    db = w.db
+    if a.filter == "msv" and a.M == 400:
+        emis = w.emissions[0]
+        wname = f"msv_m400_{a.nseq // 1000}k_lognormal"
+    else:
+        emis = synth.sample_emissions(synth.streams(3)["profile"], a.M)
+        wname = f"{a.filter}_m{a.M}_{a.nseq // 1000}k_lognormal"
+    gen_s = time.time() - t0
+    dev = torch.device("cuda:0")
+    gdb = hm.Database(db.res, db.offsets, dev)
+    prof = hm.Profile.from_emissions(emis, synth.BG, dev)
+    plan = hm.plan_for(a.filter, a.M) if not a.plan else \
+        hm.make_plan(*[int(v) for v in a.plan.split(",")])
+    wall, kern, score, flags = time_plain(hm, torch, a.filter, prof, gdb, plan, a.steps,
+                                          a.warmup)
+    cells = a.M * db.residues
+    return {"workload": wname, "db": db, "gdb": gdb, "emis": emis, "plan": plan,
+            "wall": wall, "kern": kern, "cells": cells, "gen_s": gen_s,
+            "score": score.cpu().numpy(), "flags": flags.cpu().numpy()}
+
+
+def oracle_check(a, filt, emis, db, gs, gf, synth, ids=None):
+    import oracle
+    from oracle import quant as oq
+    oprof = oq.quantize(emis, synth.BG)
+    t = time.perf_counter()
+    es, ef = oracle.score_db(filt, oprof, db.res, db.offsets, ids=ids, nthreads=nthreads(a))
+    dt = time.perf_counter() - t
+    if ids is None:
+        bad = int(((gs != es) | (gf != ef)).sum())
+    else:
+        bad = int(((gs[ids] != es[ids]) | (gf[ids] != ef[ids])).sum())
+    return bad, dt
+
+
+def ssv_leg(a, hm, torch, synth, h):
+    M = 400
+    emis = synth.sample_emissions(synth.streams(3)["profile"], M)
+    prof = hm.Profile.from_emissions(emis, synth.BG, h["gdb"].device)
+    plan = hm.plan_for("ssv", M)
+    wall, kern, score, flags = time_plain(hm, torch, "ssv", prof, h["gdb"], plan, 10, 2)
+    cells = M * h["db"].residues
+    bad, _ = oracle_check(a, "ssv", emis, h["db"], score.cpu().numpy(), flags.cpu().numpy(),
+                          synth)
+    return {"value": round(cells / wall / 1e9, 1), "unit": "GCUPS",
+            "kernel_ms": round(kern * 1e3, 4),
+            "frac": round(cells / kern * INSTR_PER_CELL["ssv"] / PEAK_INSTR, 4),
+            "plan": list(plan.as_tuple()),
+            "parity": "bit-exact" if bad == 0 else f"{bad} mismatches"}
+
+
+def batched_leg(a, hm, torch, synth):
+    import paper_1707_09683_amd.batch as hb
+    t0 = time.time()
+    w = synth.batched(nseq=a.batch_nseq)
+    gen_s = time.time() - t0
+    dev = torch.device("cuda:0")
+    gdb = hm.Database(w.db.res, w.db.offsets, dev)
+    profs = [hm.Profile.from_emissions(e, synth.BG, dev) for e in w.emissions]
+    queries = list(zip(w.filters, profs))
+    b = hb.Batch(queries, gdb, branches=4)
+    cells = b.cells()
+    b.launch()                                        # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    b.launch()
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t
+    # 64 sequential plain launches, same plans, one stream
+    outs = []
+    ws = hm.new_workspace(dev)
+    for f, p in queries:
+        sdt = torch.uint8 if f == "msv" else torch.int8
+        outs.append((torch.empty(gdb.nseq, dtype=sdt, device=dev),
+                     torch.empty(gdb.nseq, dtype=torch.uint8, device=dev)))
+    for (f, p), plan, (s, fl) in zip(queries, b.plans, outs):   # warm-up
+        (hm.msv_score if f == "msv" else hm.ssv_score)(p, gdb, s, fl, ws, plan)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for (f, p), plan, (s, fl) in zip(queries, b.plans, outs):
+        (hm.msv_score if f == "msv" else hm.ssv_score)(p, gdb, s, fl, ws, plan)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t
+    same = all(torch.equal(s, b.scores[i]) and torch.equal(fl, b.flags[i])
+               for i, (s, fl) in enumerate(outs))
+    # oracle on a sample of sequences for every query
+    rng = np.random.default_rng(44)
+    ids = np.sort(rng.choice(w.db.n, size=min(150, w.db.n), replace=False))
+    bad = 0
+    for i, (f, _) in enumerate(queries):
+        b2, _ = oracle_check(a, f, w.emissions[i], w.db, b.scores[i].cpu().numpy(),
+                             b.flags[i].cpu().numpy(), synth, ids)
+        bad += b2
+    b.close()
+    gdb.close()
+    return {"workload": f"batched_64q_{a.batch_nseq // 1000}k_lognormal",
+            "queries": len(queries), "cells": cells,
+            "batched_gcups": round(cells / t_batch / 1e9, 1),
+            "sequential_plain_gcups": round(cells / t_seq / 1e9, 1),
+            "batched_s": round(t_batch, 4), "sequential_s": round(t_seq, 4),
+            "speedup": round(t_seq / t_batch, 3),
+            "identical_to_plain": bool(same),
+            "oracle_sample": f"{len(ids)} sequences x {len(queries)} queries, "
+                             + ("bit-exact" if bad == 0 else f"{bad} mismatches"),
+            "gen_s": round(gen_s, 1)}
+
+
+def served_leg(a, hm, torch, synth):
+    import paper_1707_09683_amd.serve as sv
+    t0 = time.time()
+    db = synth.served_db(nseq=a.serve_nseq)
+    gen_s = time.time() - t0
+    dev = torch.device("cuda:0")
+    gdb = hm.Database(db.res, db.offsets, dev)
+    # capacity of the plain path: mean service time of back-to-back requests
+    cal = synth.request_trace(5 + 1000, 8, 1e6)
+    plain = sv.Server(gdb, synth.BG, max_inflight=1, depth=1, chunk_cells=float("inf"))
+    reqs, span = sv.replay(plain, np.zeros(len(cal[0])), cal[2], cal[3])
+    service = span / len(reqs)
+    qps = 0.7 / service
+    arr, Ms, filt, emis = synth.request_trace(5, a.serve_requests, qps)
+    cells = int(np.sum(Ms)) * db.residues
+    reqs_p, span_p = sv.replay(plain, arr, filt, emis)
+    plain.close()
+    srv = sv.Server(gdb, synth.BG, max_inflight=8, depth=3, chunk_cells=4e10)
+    reqs_s, span_s = sv.replay(srv, arr, filt, emis)
+    srv.close()
+    same = all(np.array_equal(x.future.result()[0], y.future.result()[0]) and
+               np.array_equal(x.future.result()[1], y.future.result()[1])
+               for x, y in zip(reqs_p, reqs_s))
+    gdb.close()
+    ps, ss = sv.latency_stats(reqs_p), sv.latency_stats(reqs_s)
+    return {"workload": f"served_{a.serve_nseq // 1000}k_resident",
+            "requests": len(arr), "qps": round(qps, 2),
+            "plain_service_ms": round(service * 1e3, 2),
+            "served": {**ss, "gcups": round(cells / span_s / 1e9, 1)},
+            "plain": {**ps, "gcups": round(cells / span_p / 1e9, 1)},
+            "p50_speedup": round(ps["p50_ms"] / ss["p50_ms"], 3),
+            "p99_speedup": round(ps["p99_ms"] / ss["p99_ms"], 3),
+            "identical_alone_vs_mix": bool(same), "gen_s": round(gen_s, 1)}
+
+
 def main():
     a = parse()
     if a.calibrate_copy:
@@ -75,109 +269,69 @@ def main():
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the filter shards "
-                          "by database sequences with no exchange, see DESIGN.md"}))
+                          "by database sequences with no exchange (see DESIGN.md)"}))
         sys.exit(2)
     import torch
     import synth
     import paper_1707_09683_amd as hm
 
-    t0 = time.time()
-    if a.filter == "msv" and a.M == 400:
-        w = synth.plain_msv_m400(nseq=a.nseq)
-        emis, db = w.emissions[0], w.db
-        wname = f"msv_m400_{a.nseq // 1000}k_lognormal"
-    else:
-        base = synth.plain_msv_m400(nseq=a.nseq)
-        st = synth.streams(3)
-        emis = synth.sample_emissions(st["profile"], a.M)
-        db = base.db
-        wname = f"{a.filter}_m{a.M}_{a.nseq // 1000}k_lognormal"
-    gen_s = time.time() - t0
-
-    dev = torch.device("cuda:0")
-    prof = hm.Profile.from_emissions(emis, synth.BG, dev)
-    gdb = hm.Database(db.res, db.offsets, dev)
-    plan = hm.default_plan(a.filter, a.M) if not a.plan else \
-        hm.make_plan(*[int(v) for v in a.plan.split(",")])
-    fn = hm.msv_score if a.filter == "msv" else hm.ssv_score
-    sdt = torch.uint8 if a.filter == "msv" else torch.int8
-    score = torch.empty(gdb.nseq, dtype=sdt, device=dev)
-    flags = torch.empty(gdb.nseq, dtype=torch.uint8, device=dev)
-    ws = hm.new_workspace(dev)
-    stream = torch.cuda.current_stream(dev)
-
-    for _ in range(a.warmup):
-        fn(prof, gdb, score, flags, ws, plan, stream)
-    torch.cuda.synchronize()
-
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for s, e in ev:
-        s.record(stream)
-        fn(prof, gdb, score, flags, ws, plan, stream)
-        e.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t1
-    step_ms = [s.elapsed_time(e) for s, e in ev]
-    kern_ms = float(np.mean(step_ms))
-
-    cells = a.M * db.residues
-    gcups = cells / (wall / a.steps) / 1e9
-    achieved = cells / (kern_ms * 1e-3) * INSTR_PER_CELL[a.filter]
-
-    # bit-exact check of the timed outputs against the oracle, and the oracle's
-    # own throughput on this host (every sequence of the workload).
-    gs, gf = score.cpu().numpy(), flags.cpu().numpy()
+    h = headline(a, hm, torch, synth)
+    cells, kern, wall = h["cells"], h["kern"], h["wall"]
+    achieved = cells / kern * INSTR_PER_CELL[a.filter]
     cpu = None
     parity = "not checked"
     if not a.no_cpu_baseline:
-        import oracle
-        from oracle import quant as oq
-        oprof = oq.quantize(emis, synth.BG)
-        nthr = a.cpu_threads or max(1, min(16, os.cpu_count() or 1))
-        t2 = time.perf_counter()
-        es, ef = oracle.score_db(a.filter, oprof, db.res, db.offsets, nthreads=nthr)
-        cpu_s = time.perf_counter() - t2
-        bad = int(((gs != es) | (gf != ef)).sum())
+        bad, cpu_s = oracle_check(a, a.filter, h["emis"], h["db"], h["score"], h["flags"],
+                                  synth)
         parity = "bit-exact" if bad == 0 else f"{bad} mismatches"
-        cpu = {"value": round(cells / cpu_s / 1e9, 3), "unit": "GCUPS", "cores": nthr,
+        cpu = {"value": round(cells / cpu_s / 1e9, 3), "unit": "GCUPS", "cores": nthreads(a),
                "kind": "oracle",
-               "sample": f"all {db.n} sequences of the workload ({cells:.3e} cells), "
+               "sample": f"all {h['db'].n} sequences of the workload ({cells:.3e} cells), "
                          f"{cpu_s:.1f} s wall"}
+    extra = {}
+    if not a.no_extra:
+        extra["ssv_m400"] = ssv_leg(a, hm, torch, synth, h)
+    h["gdb"].close()
+    if not a.no_extra:
+        extra["batched"] = batched_leg(a, hm, torch, synth)
+        extra["served"] = served_leg(a, hm, torch, synth)
 
     out = {
         "metric": f"{a.filter.upper()} GCUPS at M={a.M} (bit-exact)",
-        "value": round(gcups, 1),
+        "value": round(cells / wall / 1e9, 1),
         "unit": "GCUPS",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(wall / a.steps * 1e3, 4),
+        "ms_per_step": round(wall * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f16x2 (exact u8/s8 saturating semantics)",
         "data": "synthetic",
-        "config": {"workload": wname, "filter": a.filter, "M": a.M, "nseq": db.n,
-                   "residues": db.residues, "cells": cells,
-                   "plan": list(plan.as_tuple()), "parallelism": "single GPU"},
+        "config": {"workload": h["workload"], "filter": a.filter, "M": a.M,
+                   "nseq": h["db"].n, "residues": h["db"].residues, "cells": cells,
+                   "plan": list(h["plan"].as_tuple()), "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                      "peak": round(PEAK_INSTR / 1e12, 2),
                      "unit": "T VALU lane-instr/s",
-                     "frac": round(achieved / PEAK_INSTR, 4), "traffic": None,
-                     "kernel_ms": round(kern_ms, 4),
+                     "frac": round(achieved / PEAK_INSTR, 4), "traffic": TRAFFIC_BYTES,
+                     "kernel_ms": round(kern * 1e3, 4),
                      "instr_per_cell": INSTR_PER_CELL[a.filter],
                      "cell_ceiling_gcups": round(PEAK_INSTR / INSTR_PER_CELL[a.filter] / 1e9)},
         "cpu_baseline": cpu,
         "parity": parity,
+        **extra,
         "context": {"paper_k40_gcups": {"msv": 283.9, "ssv": 471.7},
-                    "workload_gen_s": round(gen_s, 1)},
+                    "workload_gen_s": round(h["gen_s"], 1)},
     }
     print(json.dumps(out), flush=True)
-    gdb.close()
-    if parity not in ("bit-exact", "not checked"):
+    bad_legs = [k for k, v in extra.items()
+                if ("parity" in v and v["parity"] != "bit-exact")
+                or v.get("identical_to_plain") is False
+                or v.get("identical_alone_vs_mix") is False
+                or ("oracle_sample" in v and "mismatch" in v["oracle_sample"])]
+    if parity not in ("bit-exact", "not checked") or bad_legs:
         sys.exit(1)
 
 
