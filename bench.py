@@ -40,12 +40,13 @@ sys.path.insert(0, ROOT)
 # ALU roofline.  MI355X issues one VALU instruction per lane per clock on
 # each of 256 CUs x 64 lanes at the 2.4 GHz peak engine clock.  The fewest
 # VALU instructions a cell can cost on gfx950's packed 16-bit datapath (two
-# cells per instruction): MSV = max(gamma, scB) + saturating add of
-# (dbias - cost) + half of a three-way max into scE -> 2.5 per cell pair;
-# SSV = saturating add + half a three-way max -> 1.5 per pair.
+# cells per instruction): one saturating (clamped) add of the per-node score
+# per cell pair, plus half of a three-way max into scE -> 1.5 per pair for
+# both filters.  (MSV's max with scB folds into the cell representation
+# while scB is fixed: cells are kept relative to scB.)
 CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
 PEAK_INSTR = CUS * LANES * CLOCK_HZ              # 39.3e12 lane-instructions/s
-INSTR_PER_CELL = {"msv": 1.25, "ssv": 0.75}
+INSTR_PER_CELL = {"msv": 0.75, "ssv": 0.75}
 
 # HBM bytes per dispatch of the headline kernel (rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, scaled by a 1 GiB device copy measured the same way; see
@@ -244,7 +245,7 @@ def served_leg(a, hm, torch, synth):
     cells = int(np.sum(Ms)) * db.residues
     reqs_p, span_p = sv.replay(plain, arr, filt, emis)
     plain.close()
-    srv = sv.Server(gdb, synth.BG, max_inflight=8, depth=3, chunk_cells=4e10)
+    srv = sv.Server(gdb, synth.BG, max_inflight=8, depth=3, chunk_cells=1e11, aging=1.0)
     reqs_s, span_s = sv.replay(srv, arr, filt, emis)
     srv.close()
     same = all(np.array_equal(x.future.result()[0], y.future.result()[0]) and

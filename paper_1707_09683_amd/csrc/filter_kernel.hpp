@@ -12,28 +12,36 @@
 //    per row).  Slot 0 of every group is a dummy node scored -inf, so node 1
 //    always sees -inf as its upper-left neighbour without masking the
 //    value shifted in from the neighbouring group; real node k is slot k.
-//  * Cells hold u/1024 in fp16, where u is the 8-bit filter value (MSV v,
-//    SSV d + 128).  Every value is a multiple of 2^-10 below 1, so fp16 adds
-//    and maxima are exact, the clamp modifier's floor at 0.0 is the 8-bit
-//    floor (-inf), and its cap at 1.0 is never reached before the overflow
-//    row.  A cell update is then
-//      MSV  v = clamp(max(gamma, scB) + (dbias - cost)/1024)   (Alg. 2 cell update)
-//      SSV  v = clamp(gamma + sc/1024)                          (Alg. 7 cell update)
-//    and scE = max(scE, v, v') takes two cells per v_pk_maximum3_f16
-//    (a running max, never reset per row).  The 255 (MSV) / 127 (SSV) caps
-//    are not applied; overflow is flagged from the running max instead,
-//    which is exact because no cap can fire before the first overflow row.
+//  * Cells hold u/1024 in fp16.  For SSV u = d + 128; for MSV u is the
+//    8-bit cell value v relative to scB: u = max(v, scB) - scB.  Every value
+//    is a multiple of 2^-10 below 1, so fp16 adds and maxima are exact, the
+//    clamp modifier's floor at 0.0 is the floor of the 8-bit arithmetic, and
+//    its cap at 1.0 is never reached before the overflow row.  With scB
+//    fixed, Alg. 2's cell update max(0, max(v, scB) + dbias - cost) is
+//    exactly max(u + dbias - cost, 0) on the relative value, so both filters
+//    update a cell with one clamped add:
+//      MSV  u = clamp(gamma + (dbias - cost)/1024)   (Alg. 2 cell update)
+//      SSV  u = clamp(gamma + sc/1024)               (Alg. 7 cell update)
+//    and scE = max(scE, u, u') takes two cells per v_pk_maximum3_f16 (a
+//    running max, never reset per row).  The 255 (MSV) / 127 (SSV) caps are
+//    not applied; overflow is flagged from the running max instead, which is
+//    exact because no cap can fire before the first overflow row.
 //  * Per-node scores of the 21 table rows live in LDS as fp16 pairs, laid
-//    out [row][chunk][lane][W] so each lane reads W consecutive dwords and
-//    every LDS read pass (128 bytes) is served by one group's contiguous
-//    block: no bank conflicts between groups reading different rows.
+//    out [row][chunk][copy][lane][W] so each lane reads W consecutive dwords
+//    and the groups served by one LDS read pass (256 bytes) use disjoint
+//    banks: no bank conflicts between groups reading different rows.
 //  * Sequences are handed out longest first from a global counter as groups
 //    finish (replaces the pre-packed warp blocks of Alg. 1).
 //  * MSV special states: scB only changes when the running max exceeds
 //    max(base + tec, the max it was last computed from), so rows run in
 //    tiles with scB fixed; at the tile end the group max is checked and, if
 //    it moved (or overflowed), the tile is replayed from a register
-//    checkpoint with the per-row special-state update of Alg. 2.
+//    checkpoint with the per-row special-state update of Alg. 2.  When scB
+//    rises by d, every relative cell becomes max(u - d, 0).  The running
+//    max of earlier scB values is kept as an integer.  A sequence whose
+//    cells never rise above scB has running max
+//    max(0, scB + max over its residues of max_k (dbias - cost_k)), computed
+//    at its end from a per-residue table.
 #pragma once
 #include "hmsv_internal.h"
 
@@ -45,13 +53,35 @@ constexpr uint32_t kMinus2 = 0xC000u;        // fp16 -2.0: score of dummy/paddin
 constexpr int kBase = 190;
 constexpr int kTec = 3;
 
-// Width in dwords of one lane's LDS read: 32 lanes x 4 bytes per pass, so a
-// group of G lanes fills a pass with W = 32 / G dwords each (1 to 4).
+// LDS reads.  gfx950's LDS serves 256 bytes (64 banks) per pass, so a
+// read instruction of w dwords per lane is served 64/w lanes at a time.
+// A lane's Q score pairs are read in chunks: full chunks of W dwords
+// (W = 64/G for groups of G >= 16 lanes, so one group fills a pass; W = 4,
+// the widest read, for narrower groups), then a 2-dword and/or a 1-dword
+// tail.  Groups that share a pass read different table rows; to keep them
+// on disjoint banks every chunk of width w is stored copies(w) = 64/(G w)
+// times side by side and group g reads copy g % copies(w).
 template <int G>
-constexpr int read_width() { return G >= 32 ? 1 : (G >= 16 ? 2 : 4); }
+constexpr int read_width() { return G >= 16 ? 64 / G : 4; }
 
 template <int G, int Q>
-constexpr int padded_q() { return (Q + read_width<G>() - 1) / read_width<G>() * read_width<G>(); }
+struct Layout {
+    static constexpr int W = read_width<G>();
+    static constexpr int NF = Q / W;                  // full chunks
+    static constexpr int R = Q - NF * W;              // tail dwords (0..W-1)
+    static constexpr bool T2 = (R & 2) != 0;
+    static constexpr bool T1 = (R & 1) != 0;
+    static constexpr int copies(int w) { return 64 / (G * w) > 1 ? 64 / (G * w) : 1; }
+    static constexpr int CW = copies(W) * G * W;      // dwords of one full chunk, all copies
+    static constexpr int OFF2 = NF * CW;
+    static constexpr int OFF1 = OFF2 + (T2 ? copies(2) * G * 2 : 0);
+    static constexpr int RS = OFF1 + (T1 ? copies(1) * G : 0);   // dwords per table row
+    static constexpr int Q2 = NF * W;                 // first register of the 2-dword tail
+    static constexpr int Q1 = NF * W + (T2 ? 2 : 0);  // register of the 1-dword tail
+    __device__ static int lane_off(int lane, int w) {
+        return ((lane / G) % copies(w)) * G * w + (lane % G) * w;
+    }
+};
 
 __device__ __forceinline__ h2 as_h2(uint32_t v) { return __builtin_bit_cast(h2, v); }
 __device__ __forceinline__ uint32_t as_u32(h2 v) { return __builtin_bit_cast(uint32_t, v); }
@@ -124,59 +154,63 @@ __device__ __forceinline__ uint32_t slot_bits(const KArgs &a, int x, int s) {
 
 template <int G, int Q, bool MSV>
 struct Lane {
-    static constexpr int W = read_width<G>();
-    static constexpr int RS = padded_q<G, Q>() * G;     // dwords per table row
+    using Lay = Layout<G, Q>;
+    static constexpr int W = Lay::W;
+    static constexpr int RS = Lay::RS;
     uint32_t R[Q];
     uint32_t xE;
-    uint32_t xB;
 
-    __device__ __forceinline__ void reset(uint32_t xb) {
+    __device__ __forceinline__ void reset() {
 #pragma unroll
         for (int q = 0; q < Q; ++q) R[q] = 0u;
         xE = 0u;
-        xB = xb;
     }
 
-    // Score pairs of row x for this lane (T = lds + j*W).
-    __device__ __forceinline__ void load_row(const uint32_t *T, uint32_t x, uint32_t (&c)[Q]) {
-        const uint32_t *t = T + x * (uint32_t)RS;
+    // MSV: scB rose by d units; every relative cell becomes max(u - d, 0).
+    __device__ __forceinline__ void lower(int d) {
+        const uint32_t m = units_splat(-d);
 #pragma unroll
-        for (int ch = 0; ch * W < Q; ++ch) {
-            const uint32_t *p = t + ch * G * W;
-            if (ch * W + W <= Q) {
-                if constexpr (W == 4) {
-                    uint4 v = *(const uint4 *)p;
-                    c[ch * 4 + 0] = v.x; c[ch * 4 + 1] = v.y;
-                    c[ch * 4 + 2] = v.z; c[ch * 4 + 3] = v.w;
-                } else if constexpr (W == 2) {
-                    uint2 v = *(const uint2 *)p;
-                    c[ch * 2 + 0] = v.x; c[ch * 2 + 1] = v.y;
-                } else {
-                    c[ch] = p[0];
-                }
+        for (int q = 0; q < Q; ++q) R[q] = add_clamp(R[q], m);
+    }
+
+    // Score pairs of row x for this lane.  TW/T2/T1: the lane's base in the
+    // LDS image for full chunks and the two tails.
+    __device__ __forceinline__ void load_row(const uint32_t *TW, const uint32_t *T2,
+                                             const uint32_t *T1, uint32_t x,
+                                             uint32_t (&c)[Q]) {
+        const uint32_t rb = x * (uint32_t)RS;
+#pragma unroll
+        for (int ch = 0; ch < Lay::NF; ++ch) {
+            const uint32_t *p = TW + rb + ch * Lay::CW;
+            if constexpr (W == 4) {
+                uint4 v = *(const uint4 *)p;
+                c[ch * 4 + 0] = v.x; c[ch * 4 + 1] = v.y;
+                c[ch * 4 + 2] = v.z; c[ch * 4 + 3] = v.w;
+            } else if constexpr (W == 2) {
+                uint2 v = *(const uint2 *)p;
+                c[ch * 2 + 0] = v.x; c[ch * 2 + 1] = v.y;
             } else {
-                const int r = Q - ch * W;      // 1..W-1 dwords left
-                if (r >= 2) {
-                    uint2 v = *(const uint2 *)p;
-                    c[ch * W + 0] = v.x; c[ch * W + 1] = v.y;
-                    if (r == 3) c[ch * W + 2] = p[2];
-                } else {
-                    c[ch * W] = p[0];
-                }
+                c[ch] = p[0];
             }
         }
+        if constexpr (Lay::T2) {
+            uint2 v = *(const uint2 *)(T2 + rb);
+            c[Lay::Q2] = v.x;
+            c[Lay::Q2 + 1] = v.y;
+        }
+        if constexpr (Lay::T1) c[Lay::Q1] = T1[rb];
     }
 
     // One residue row of Alg. 2 (MSV) / Alg. 7 (SSV): shift, fetch, cell update.
-    __device__ __forceinline__ void row(const uint32_t *T, uint32_t x) {
+    __device__ __forceinline__ void row(const uint32_t *const (&T)[3], uint32_t x) {
         uint32_t c[Q];
-        load_row(T, x, c);
+        load_row(T[0], T[1], T[2], x, c);
         uint32_t gam = shift_in(R[Q - 1]);
         uint32_t prev_v = 0;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             uint32_t old = R[q];
-            uint32_t v = MSV ? add_clamp(hmax(gam, xB), c[q]) : add_clamp(gam, c[q]);
+            uint32_t v = add_clamp(gam, c[q]);
             R[q] = v;
             if (q & 1) xE = hmax3(xE, prev_v, v);
             else prev_v = v;
@@ -193,6 +227,7 @@ filter_kernel(KArgs a) {
     using L = Lane<G, Q, MSV>;
     constexpr int W = L::W;
     constexpr int RS = L::RS;
+    static_assert(RS % 4 == 0, "rows must stay 16-byte aligned");
 
     // Stage the profile image (built by prep_kernel) into LDS.
     {
@@ -206,18 +241,32 @@ filter_kernel(KArgs a) {
     const int lane = threadIdx.x & 63;
     const int j = lane % G;
     const bool gstart = (j == 0);
-    const uint32_t *T = lds + j * W;
+    using Lay = typename L::Lay;
+    const uint32_t *T[3] = {lds + Lay::lane_off(lane, W),
+                            lds + Lay::OFF2 + Lay::lane_off(lane, 2),
+                            lds + Lay::OFF1 + Lay::lane_off(lane, 1)};
     const int dbias = a.dbias;
 
     L st;
     uint32_t off = a.pad_off;
     int rows_left = 0x7fffffff;
     uint32_t id = 0;
+    uint32_t seq_off = 0;
+    int seq_rows = 0;
     int tjbm = 0;
-    int built = -(1 << 30);
+    int xb = 0;                  // MSV: scB (integer filter units)
+    int cm = -1;                 // MSV: exact running max of earlier scB epochs
+    int built = -(1 << 30);      // MSV: running max scB was last computed from
     bool ovf = false;
     bool active = false;
     bool need = true;   // group wants a sequence
+
+    // MSV running max = max(cm, current epoch's max + scB); -1 while the
+    // current epoch never rose above scB.
+    auto epoch_max = [&]() -> int {
+        int m = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
+        return m > 0 ? m + xb : -1;
+    };
 
     for (;;) {
         // ---- hand sequences to groups that need one (uniform) ----------
@@ -244,9 +293,12 @@ filter_kernel(KArgs a) {
                     rows_left = 0x7fffffff;
                     active = false;
                 }
-                int xb0 = kBase - tjbm;
-                xb0 = xb0 < 0 ? 0 : xb0;
-                st.reset(units_splat(xb0));
+                seq_off = off;
+                seq_rows = rows_left;
+                xb = kBase - tjbm;
+                xb = xb < 0 ? 0 : xb;
+                st.reset();
+                cm = -1;
                 built = -(1 << 30);
                 ovf = false;
                 need = false;
@@ -284,7 +336,8 @@ filter_kernel(KArgs a) {
 
         if constexpr (MSV) {
             // ---- special states: did scB move in this tile? -------------
-            int mx = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
+            int em = epoch_max();
+            int mx = cm > em ? cm : em;
             int lim = built > kBase + kTec ? built : kBase + kTec;
             bool trig = active && !ovf && (mx > lim || mx >= 255 - dbias);
             if (__any(trig)) {
@@ -297,12 +350,18 @@ filter_kernel(KArgs a) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         st.row(T, (ww >> (8 * r)) & 0xffu);
-                        int m2 = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
+                        int e2 = epoch_max();
+                        int m2 = cm > e2 ? cm : e2;
                         if (m2 >= 255 - dbias) ovf = true;
                         int j2 = m2 - kTec > kBase ? m2 - kTec : kBase;
-                        int xb = j2 - tjbm;
-                        xb = xb < 0 ? 0 : (xb > 255 ? 255 : xb);
-                        st.xB = units_splat(xb);
+                        int xbn = j2 - tjbm;
+                        xbn = xbn < 0 ? 0 : (xbn > 255 ? 255 : xbn);
+                        if (xbn > xb) {          // new scB epoch
+                            st.lower(xbn - xb);
+                            st.xE = 0u;
+                            cm = m2;
+                            xb = xbn;
+                        }
                         built = m2;
                     }
                     o += step;
@@ -312,7 +371,26 @@ filter_kernel(KArgs a) {
 
         // ---- finished sequences: record scores (Alg. 2 end-residue branch) -----
         if (__any(ended)) {
-            int mx = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
+            int mx;
+            if constexpr (MSV) {
+                int em = epoch_max();
+                mx = cm > em ? cm : em;
+                // never above scB: max(0, scB + best score of its residues)
+                int bst = -(1 << 30);
+                if (ended && mx < 0) {
+                    for (int i = j; i < seq_rows; i += G) {
+                        int v = a.best[a.res[seq_off + i]];
+                        bst = v > bst ? v : bst;
+                    }
+                }
+                bst = group_max<G>(bst);
+                if (mx < 0) {
+                    int v = xb + bst;
+                    mx = v > 0 ? v : 0;
+                }
+            } else {
+                mx = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
+            }
             if (ended && gstart) {
                 uint8_t sc, fl;
                 if constexpr (MSV) {
@@ -333,13 +411,29 @@ filter_kernel(KArgs a) {
     }
 }
 
-// LDS image of the profile: dword (x, q, j) at x*RS + (q/W)*G*W + j*W + q%W
-// holds slots (q + 2jQ, q + (2j+1)Q) as two fp16 scores.  Thread 0 also
-// resets the work-queue counter.
 template <int G, int Q, bool MSV>
-__global__ void __launch_bounds__(256) prep_kernel(KArgs a) {
-    constexpr int W = read_width<G>();
-    constexpr int RS = padded_q<G, Q>() * G;
+__global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks) {
+    using Lay = Layout<G, Q>;
+    constexpr int RS = Lay::RS;
+    if ((int)blockIdx.x >= image_blocks) {
+        // MSV: best[x] = max_k (dbias - cost_k(x)) for each table row x
+        __shared__ int red[256];
+        int x = blockIdx.x - image_blocks;
+        int m = -(1 << 30);
+        for (int k = threadIdx.x; k < a.M; k += blockDim.x) {
+            int v = a.dbias - (int)a.cost[x * a.M + k];
+            m = v > m ? v : m;
+        }
+        red[threadIdx.x] = m;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h && red[threadIdx.x + h] > red[threadIdx.x])
+                red[threadIdx.x] = red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) a.best[x] = red[0];
+        return;
+    }
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx == 0) {
         a.counter[0] = 0u;
@@ -348,22 +442,34 @@ __global__ void __launch_bounds__(256) prep_kernel(KArgs a) {
     if (idx >= kRows * RS) return;
     int x = idx / RS;
     int rem = idx - x * RS;
-    int ch = rem / (G * W);
-    int r2 = rem - ch * G * W;
-    int jj = r2 / W;
-    int qq = ch * W + (r2 - jj * W);
-    uint32_t v = (kMinus2 << 16) | kMinus2;
-    if (qq < Q) {
-        int s0 = qq + Q * (2 * jj);
-        v = slot_bits<MSV>(a, x, s0) | (slot_bits<MSV>(a, x, s0 + Q) << 16);
+    int w, q0;
+    if (rem < Lay::OFF2) {
+        int ch = rem / Lay::CW;
+        rem -= ch * Lay::CW;
+        w = Lay::W;
+        q0 = ch * Lay::W;
+    } else if (rem < Lay::OFF1) {
+        rem -= Lay::OFF2;
+        w = 2;
+        q0 = Lay::Q2;
+    } else {
+        rem -= Lay::OFF1;
+        w = 1;
+        q0 = Lay::Q1;
     }
-    a.image[idx] = v;
+    rem %= G * w;                                  // same data in every copy
+    int jj = rem / w;
+    int qq = q0 + (rem - jj * w);
+    int s0 = qq + Q * (2 * jj);
+    a.image[idx] = slot_bits<MSV>(a, x, s0) | (slot_bits<MSV>(a, x, s0 + Q) << 16);
 }
 
 template <int G, int Q, bool MSV>
 hipError_t launch_filter(const KArgs &a, int wpb, int blocks, hipStream_t s) {
-    constexpr int n = kRows * padded_q<G, Q>() * G;
-    hipLaunchKernelGGL((prep_kernel<G, Q, MSV>), dim3((n + 255) / 256), dim3(256), 0, s, a);
+    constexpr int n = kRows * Layout<G, Q>::RS;
+    constexpr int nb = (n + 255) / 256;
+    hipLaunchKernelGGL((prep_kernel<G, Q, MSV>), dim3(nb + (MSV ? kRows : 0)), dim3(256), 0, s,
+                       a, nb);
     size_t lds = lds_bytes(G, Q);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)filter_kernel<G, Q, MSV>,

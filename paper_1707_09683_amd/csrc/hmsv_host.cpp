@@ -142,6 +142,7 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
     a.flag = flags;
     a.counter = (uint32_t *)workspace;
     a.image = (uint32_t *)((char *)workspace + kWsCounterBytes);
+    a.best = (int32_t *)((char *)workspace + 64);
     if (((uintptr_t)workspace & 255u) != 0) return HMSV_EINVAL;
 
     int blocks = plan.blocks;

@@ -36,9 +36,11 @@ struct KArgs {
     uint8_t *flag;
     uint32_t *counter;     // work-queue head, zeroed by the prep kernel
     uint32_t *image;       // LDS image of the profile (workspace), 16-byte aligned
+    int32_t *best;         // MSV: per table row, max over nodes of dbias - cost (workspace)
 };
 
-// Workspace layout: queue counters, then the profile's LDS image.
+// Workspace layout: queue counters (bytes 0..63), the MSV per-residue best
+// scores (bytes 64..147), then the profile's LDS image from byte 256.
 constexpr size_t kWsCounterBytes = 256;
 constexpr size_t kWsBytes = kWsCounterBytes + 160 * 1024;
 
@@ -54,12 +56,15 @@ struct KernelEntry {
     OccupancyFn occupancy;
 };
 
-// LDS read width per lane (dwords) and the table's padded register count.
-inline int read_width_host(int G) { return G >= 32 ? 1 : (G >= 16 ? 2 : 4); }
+// Size of a plan's LDS image: mirrors Layout in filter_kernel.hpp (full
+// chunks of W dwords and 2-/1-dword tails, each stored 64/(G w) times).
 inline size_t lds_bytes(int G, int Q) {
-    int W = read_width_host(G);
-    int qp = (Q + W - 1) / W * W;
-    return (size_t)kRows * G * qp * 4;
+    int W = G >= 16 ? 64 / G : 4;
+    auto copies = [G](int w) { return 64 / (G * w) > 1 ? 64 / (G * w) : 1; };
+    int nf = Q / W, r = Q - nf * W;
+    size_t rs = (size_t)nf * copies(W) * G * W + ((r & 2) ? (size_t)copies(2) * G * 2 : 0) +
+                ((r & 1) ? (size_t)copies(1) * G : 0);
+    return (size_t)kRows * rs * 4;
 }
 // A group of G lanes with Q registers covers nodes 1..2GQ-1 (slot 0 is a
 // dummy -inf node).

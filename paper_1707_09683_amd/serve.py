@@ -8,7 +8,9 @@ small tables).  A request's search is split into chunks: contiguous ranges
 of the database's longest-first processing order holding about
 ``chunk_cells`` cells each.  The scheduler keeps up to ``depth`` chunks on
 the GPU; whenever one finishes it issues the next chunk of the admitted
-request with the least remaining work (its own stream, so chunks of one
+request with the earliest key "arrival + aging x remaining work / rate"
+(FIFO at aging 0, shortest-remaining-work first as aging grows; its own
+stream, so chunks of one
 request stay ordered and chunks of different requests overlap on the
 device), provided the LDS images of the chunks then in flight fit one CU's
 LDS together (``lds_budget``) so they can actually co-reside.  Requests
@@ -74,8 +76,8 @@ class _Slot:
 
 class Server:
     def __init__(self, db: Database, bg, device="cuda", max_inflight=8, depth=3,
-                 chunk_cells=4e10, hbm_budget=2 << 30, lds_budget=160 * 1024,
-                 poll_s=100e-6):
+                 chunk_cells=1e11, hbm_budget=2 << 30, lds_budget=160 * 1024,
+                 poll_s=100e-6, aging=1.0, rate=2.0e13):
         self.db = db
         self.bg = np.asarray(bg, dtype=np.float64)
         self.device = torch.device(device)
@@ -86,6 +88,12 @@ class Server:
         self.chunk_cells = chunk_cells
         self.lds_budget = lds_budget
         self.poll_s = poll_s
+        # priority key = arrival time + aging * remaining cells / rate: aging 0
+        # is FIFO, large aging is shortest-remaining-work first; in between,
+        # short requests overtake long ones only while the long ones have not
+        # waited longer than their own remaining run time (scaled by aging).
+        self.aging = aging
+        self.rate = rate
         order = db.order()
         self._order = order
         self._cum = None
@@ -168,7 +176,8 @@ class Server:
             # request run in order on its stream and never co-reside)
             running = {id(r): r.lds for r, _, _ in self._inflight}
             used = sum(running.values())
-            cands = sorted(self._active, key=lambda r: (r.remaining, r.rid))
+            cands = sorted(self._active, key=lambda r: (
+                r.t_arrival + self.aging * r.remaining / self.rate, r.rid))
             r = next((c for c in cands if not running or id(c) in running
                       or used + c.lds <= self.lds_budget), None)
             if r is None:

@@ -12,7 +12,12 @@ I3  rows of non-scoring residues appended after a target (row padding) change
     neither the running maximum nor the score;
 I4  scB only changes when the running maximum passes max(base + tec, the value
     scB was last computed from), so rows can be run in tiles with scB fixed,
-    checked at the tile end, and replayed row by row only when it moved.
+    checked at the tile end, and replayed row by row only when it moved;
+I5  with scB fixed, the MSV cell update max(0, max(v, scB) + s) becomes one
+    floored add on w = max(v, scB) - scB:  w' = max(w + s, 0).  When scB
+    rises by d, every w becomes max(w - d, 0).  A row whose w are all 0 has
+    maximum max(0, scB + max_k s_k(x)), so a sequence that never rises above
+    scB has running maximum max(0, scB + max over its residues of max_k s_k).
 """
 import numpy as np
 
@@ -60,6 +65,64 @@ def model_msv(prof, x, tile=8, pad=4):
     return (255, 1) if flag else (max(0, run - tec), 0)
 
 
+def model_msv_w(prof, x, tile=8, pad=4):
+    """The kernel's MSV: relative cells w (I5), lazy scB tiles (I4)."""
+    M, bias = prof["M"], prof["bias"]
+    s = bias - prof["cost"].astype(np.int64)
+    best = s.max(axis=1)                      # max_k s_k(x) per residue
+    L = len(x)
+    rows = list(x) + [20] * ((-L) % pad if L else pad)
+    tjbm = q.tjb(L) + prof["tbm"]
+    tec, base = q.tec(), q.BASE
+
+    def xb_of(m):
+        return max(0, max(base, m - tec) - tjbm)
+
+    xb = xb_of(-(1 << 30))
+    Wc = np.zeros(M, np.int64)            # relative cells
+    run = 0                               # running max of w in this scB epoch
+    cm = -1                               # exact running max of earlier epochs
+    built = -(1 << 30)
+    flag = False
+
+    def cummax():
+        return max(cm, run + xb if run > 0 else -1)
+
+    i = 0
+    while i < len(rows):
+        n = min(tile, len(rows) - i)
+        ck_W, ck_run = Wc.copy(), run
+        for t in range(n):
+            g = np.concatenate(([0], Wc[:-1]))
+            Wc = np.maximum(0, g + s[rows[i + t]])
+            run = max(run, int(Wc.max()))
+        c = cummax()
+        moved = c > max(base + tec, built) or c >= 255 - bias
+        if moved and not flag:
+            Wc, run = ck_W, ck_run
+            for t in range(n):
+                g = np.concatenate(([0], Wc[:-1]))
+                Wc = np.maximum(0, g + s[rows[i + t]])
+                run = max(run, int(Wc.max()))
+                c = cummax()
+                if c >= 255 - bias:
+                    flag = True
+                xbn = xb_of(c)
+                if xbn > xb:                    # new scB epoch
+                    Wc = np.maximum(0, Wc - (xbn - xb))
+                    cm = max(cm, c)
+                    run = 0
+                    xb = xbn
+                built = c
+        i += n
+    c = cummax()
+    if c < 0:                                   # never above scB: exact from the residues
+        c = max(0, xb + int(max(best[r] for r in rows)))
+    if flag or c >= 255 - bias:
+        return 255, 1
+    return max(0, c - tec), 0
+
+
 def model_ssv(prof, x, pad=4):
     M = prof["M"]
     sc = prof["sc"].astype(np.int64)
@@ -88,8 +151,36 @@ def test_msv_kernel_reformulation_matches_oracle():
             exp = oracle.msv_seq(prof, x)
             for tile in (4, 8, 32):
                 assert model_msv(prof, x, tile) == exp, (trial, sidx, tile)
+                assert model_msv_w(prof, x, tile) == exp, (trial, sidx, tile, "w")
             regimes["ovf" if exp[1] else ("j" if exp[0] > q.BASE else "plain")] += 1
     assert min(regimes.values()) > 3, regimes
+
+
+def test_msv_relative_cells_edge_cases():
+    """I5 on sequences that never rise above scB (all-invalid, empty, and
+    residues whose best score is negative) and on a profile where every
+    residue but one scores below zero."""
+    rng = np.random.default_rng(23)
+    for M in (1, 5, 40):
+        prof = q.quantize(synth.sample_emissions(rng, M), synth.BG)
+        for x in (np.zeros(0, np.uint8), np.full(7, 20, np.uint8), np.full(3, 31, np.uint8)):
+            assert model_msv_w(prof, x) == oracle.msv_seq(prof, x)
+        s = prof["bias"] - prof["cost"].astype(int)
+        neg = [a for a in range(20) if s[a].max() < 0]
+        if neg:
+            for L in (1, 4, 9, 30):
+                x = rng.choice(neg, size=L).astype(np.uint8)
+                assert model_msv_w(prof, x) == oracle.msv_seq(prof, x)
+    # a hand-made profile: only residue 0 scores positive anywhere
+    M = 6
+    cost = np.full((32, M), 255, np.uint8)
+    cost[:20] = 40
+    cost[0] = 0
+    prof = {"cost": cost, "sc": np.maximum(-128, 20 - cost.astype(int)).astype(np.int8),
+            "bias": 20, "M": M, "tbm": q.tbm(M)}
+    for xs in ([1, 2, 3], [5] * 11, [0, 1, 0, 1], [3, 0, 0, 0, 0, 0, 0, 9]):
+        x = np.array(xs, np.uint8)
+        assert model_msv_w(prof, x) == oracle.msv_seq(prof, x)
 
 
 def test_ssv_kernel_reformulation_matches_oracle():
