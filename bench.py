@@ -48,10 +48,24 @@ CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
 PEAK_INSTR = CUS * LANES * CLOCK_HZ              # 39.3e12 lane-instructions/s
 INSTR_PER_CELL = {"msv": 0.75, "ssv": 0.75}
 
-# HBM bytes per dispatch of the headline kernel (rocprofv3 FETCH_SIZE and
-# WRITE_SIZE, scaled by a 1 GiB device copy measured the same way; see
-# profiles/).  None until taken on the current kernel build.
-TRAFFIC_BYTES = None
+# HBM bytes per dispatch of the headline kernel come from rocprofv3
+# FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB device copy measured the same
+# way (profiles/traffic_*.json).  A record is used only if it was taken on
+# the current kernel source and the same plan and workload.
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def traffic_for(workload, plan):
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1707_09683_amd", "csrc", "filter_kernel.hpp")
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    for f in glob.glob(os.path.join(PROFILES, "traffic_*.json")):
+        rec = json.load(open(f))
+        if rec.get("kernel_source_sha1") == sha and rec.get("workload") == workload \
+                and list(rec.get("plan", [])) == list(plan):
+            return rec["bytes_per_launch"]
+    return None
 
 
 def parse():
@@ -316,7 +330,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                      "peak": round(PEAK_INSTR / 1e12, 2),
                      "unit": "T VALU lane-instr/s",
-                     "frac": round(achieved / PEAK_INSTR, 4), "traffic": TRAFFIC_BYTES,
+                     "frac": round(achieved / PEAK_INSTR, 4),
+                     "traffic": traffic_for(h["workload"], h["plan"].as_tuple()),
                      "kernel_ms": round(kern * 1e3, 4),
                      "instr_per_cell": INSTR_PER_CELL[a.filter],
                      "cell_ceiling_gcups": round(PEAK_INSTR / INSTR_PER_CELL[a.filter] / 1e9)},
