@@ -114,7 +114,7 @@ def time_plain(hm, torch, filt, prof, gdb, plan, steps, warmup):
     sdt = torch.uint8 if filt == "msv" else torch.int8
     score = torch.empty(gdb.nseq, dtype=sdt, device=dev)
     flags = torch.empty(gdb.nseq, dtype=torch.uint8, device=dev)
-    ws = hm.new_workspace(dev)
+    ws = hm.new_workspace(dev, gdb.nseq)
     stream = torch.cuda.current_stream(dev)
     for _ in range(warmup):
         fn(prof, gdb, score, flags, ws, plan, stream)
@@ -205,7 +205,7 @@ def batched_leg(a, hm, torch, synth):
     t_batch = time.perf_counter() - t
     # 64 sequential plain launches, same plans, one stream
     outs = []
-    ws = hm.new_workspace(dev)
+    ws = hm.new_workspace(dev, gdb.nseq)
     for f, p in queries:
         sdt = torch.uint8 if f == "msv" else torch.int8
         outs.append((torch.empty(gdb.nseq, dtype=sdt, device=dev),

@@ -110,8 +110,8 @@ int64_t hmsv_db_padded_rows(const hmsv_db *db);  /* rows the kernels run */
  * group covers 2*G*Q - 1 >= M nodes (one cell is a fixed -inf node).  64/G sequences share a wavefront (the
  * paper's multi-sequence alignment, Sec. 3.1 tier 4).  waves_per_block
  * wavefronts share one LDS copy of the profile; blocks = 0 picks a
- * persistent grid of the resident maximum.  tile is the number of rows
- * (multiple of 4) between checks of the MSV special states. */
+ * persistent grid of the resident maximum.  tile is kept for plan-table
+ * compatibility (a multiple of 4) and no longer affects the kernels. */
 typedef struct {
     int32_t G;
     int32_t Q;
@@ -123,9 +123,10 @@ typedef struct {
 /* The library's default plan for a filter ("msv" = 1, "ssv" = 0) and M. */
 hmsv_status hmsv_default_plan(int32_t is_msv, int32_t M, hmsv_plan *plan);
 
-/* Device workspace needed by a scoring call (bytes, fixed: the work-queue
- * counters plus the profile converted to the kernel's LDS layout). */
-size_t hmsv_workspace_bytes(void);
+/* Device workspace needed by a scoring call on a database of nseq
+ * sequences (bytes): the work-queue counters, the MSV per-residue best
+ * scores and the profile converted to the kernel's LDS layout. */
+size_t hmsv_workspace_bytes(int64_t nseq);
 
 /* ---- scoring -----------------------------------------------------------
  * MSV (paper Alg. 2): score[i] = raw 8-bit MSV score of sequence i (the
@@ -133,7 +134,7 @@ size_t hmsv_workspace_bytes(void);
  * SSV (paper Alg. 7): score[i] = best single-segment score in signed 8-bit
  * (-128 = no positive segment), flags[i] = 1 on saturation (score = 127).
  * score, flags: device, [nseq] each, written for every sequence.
- * workspace: device, hmsv_workspace_bytes() bytes, 256-byte aligned,
+ * workspace: device, hmsv_workspace_bytes(nseq) bytes, 256-byte aligned,
  * caller-owned; its content need not be initialised; calls that share a
  * workspace must be ordered on one stream.  plan: NULL for the default.  The call allocates nothing.
  * Fails with HMSV_EINVAL on null pointers or a profile outside its
@@ -187,7 +188,7 @@ typedef struct {
     hmsv_profile prof;
     void *score;        /* device, [nseq] */
     uint8_t *flags;     /* device, [nseq] */
-    void *workspace;    /* device, hmsv_workspace_bytes() */
+    void *workspace;    /* device, hmsv_workspace_bytes(nseq) */
     hmsv_plan plan;     /* plan.G == 0: default */
 } hmsv_query;
 

@@ -48,7 +48,7 @@ class _CProfile(ctypes.Structure):
 
 class Plan(ctypes.Structure):
     """Launch plan (hmsv_plan): group width G, registers per lane Q,
-    waves per block, blocks (0 = persistent), MSV special-state tile."""
+    waves per block, blocks (0 = persistent), tile (kept for ABI compatibility, unused)."""
     _fields_ = [("G", ctypes.c_int32), ("Q", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32),
                 ("tile", ctypes.c_int32)]
@@ -81,7 +81,7 @@ for _f in ("hmsv_db_nseq", "hmsv_db_residues", "hmsv_db_padded_rows"):
 _lib.hmsv_default_plan.restype = ctypes.c_int
 _lib.hmsv_default_plan.argtypes = [_i32, _i32, ctypes.POINTER(Plan)]
 _lib.hmsv_workspace_bytes.restype = ctypes.c_size_t
-_lib.hmsv_workspace_bytes.argtypes = []
+_lib.hmsv_workspace_bytes.argtypes = [_i64]
 for _f in ("hmsv_msv_score", "hmsv_ssv_score"):
     getattr(_lib, _f).restype = ctypes.c_int
     getattr(_lib, _f).argtypes = [ctypes.POINTER(_CProfile), _P, _P, _P, _P,
@@ -220,12 +220,13 @@ def plan_for(filt: str, M: int) -> Plan:
     return make_plan(*t) if t else default_plan(filt, M)
 
 
-def workspace_bytes() -> int:
-    return int(_lib.hmsv_workspace_bytes())
+def workspace_bytes(nseq: int) -> int:
+    """Workspace bytes for scoring calls on a database of nseq sequences."""
+    return int(_lib.hmsv_workspace_bytes(int(nseq)))
 
 
-def new_workspace(device="cuda") -> torch.Tensor:
-    return torch.zeros(workspace_bytes(), dtype=torch.uint8, device=device)
+def new_workspace(device="cuda", nseq: int = 0) -> torch.Tensor:
+    return torch.zeros(workspace_bytes(nseq), dtype=torch.uint8, device=device)
 
 
 def _score(filt, profile: Profile, db: Database, score, flags, workspace, plan, stream,
@@ -238,13 +239,13 @@ def _score(filt, profile: Profile, db: Database, score, flags, workspace, plan, 
     if flags is None:
         flags = torch.empty(n, dtype=torch.uint8, device=dev)
     if workspace is None:
-        workspace = new_workspace(dev)
+        workspace = new_workspace(dev, n)
     if score.dtype != sdt or flags.dtype != torch.uint8:
         raise TypeError("score/flags dtype")
     if score.numel() < n or flags.numel() < n or not score.is_contiguous() \
             or not flags.is_contiguous():
         raise ValueError("score/flags must be contiguous with >= nseq entries")
-    if workspace.numel() * workspace.element_size() < workspace_bytes():
+    if workspace.numel() * workspace.element_size() < workspace_bytes(n):
         raise ValueError("workspace too small")
     for t in (score, flags, workspace):
         if t.device != dev:

@@ -1,4 +1,4 @@
-"""Autotuner for launch plans: group width, waves per block, MSV tile.
+"""Autotuner for launch plans: group width and waves per block.
 
 For each filter and each profile length of a grid of M-bins, every valid
 plan is timed on a lognormal database sample with HIP events (mean of
@@ -25,7 +25,6 @@ M_BINS = (30, 40, 48, 64, 80, 96, 128, 160, 192, 256, 320, 400, 512, 640, 768, 1
           1280, 1536, 2048, 2400, 3072, 3839)
 GROUPS = (4, 8, 16, 32, 64)
 WAVES = (2, 4, 8)
-TILES_MSV = (32, 64, 128)
 QMAX = 32
 LDS_LIMIT = 160 * 1024
 
@@ -52,8 +51,7 @@ def candidates(filt, M):
         if Q > QMAX or lds_bytes(G, Q) > LDS_LIMIT:
             continue
         for wpb in WAVES:
-            for tile in (TILES_MSV if filt == "msv" else (64,)):
-                yield (G, Q, wpb, 0, tile)
+            yield (G, Q, wpb, 0, 64)
 
 
 def device_key():
@@ -94,7 +92,7 @@ def tune(nseq=500_000, bins=M_BINS, filters=("msv", "ssv"), reps=4, seed=2, log=
     st = synth.streams(seed)
     db_np, _ = synth.lognormal_db(seed, nseq, None, 0.0, st)
     db = Database(db_np.res, db_np.offsets, dev)
-    ws = new_workspace(dev)
+    ws = new_workspace(dev, db.nseq)
     out = {}
     for filt in filters:
         fn = msv_score if filt == "msv" else ssv_score

@@ -54,7 +54,7 @@ class Batch:
             sdt = torch.uint8 if filt == "msv" else torch.int8
             s = torch.empty(n, dtype=sdt, device=dev)
             f = torch.empty(n, dtype=torch.uint8, device=dev)
-            ws = torch.zeros(workspace_bytes(), dtype=torch.uint8, device=dev)
+            ws = torch.zeros(workspace_bytes(n), dtype=torch.uint8, device=dev)
             p = plans[i] if plans is not None and plans[i] is not None else plan_for(filt, prof.M)
             self.scores.append(s)
             self.flags.append(f)

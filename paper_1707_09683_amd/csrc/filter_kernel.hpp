@@ -32,14 +32,11 @@
 //    banks: no bank conflicts between groups reading different rows.
 //  * Sequences are handed out longest first from a global counter as groups
 //    finish (replaces the pre-packed warp blocks of Alg. 1).
-//  * MSV special states: scB only changes when the running max exceeds
-//    max(base + tec, the max it was last computed from), so rows run in
-//    tiles with scB fixed; at the tile end the group max is checked and, if
-//    it moved (or overflowed), the tile is replayed from a register
-//    checkpoint with the per-row special-state update of Alg. 2.  When scB
-//    rises by d, every relative cell becomes max(u - d, 0).  The running
-//    max of earlier scB values is kept as an integer.  A sequence whose
-//    cells never rise above scB has running max
+//  * MSV special states: scB fixed first, exact replay when needed (see
+//    filter_kernel).  When scB rises by
+//    d, every relative cell becomes max(u - d, 0); the running max of
+//    earlier scB values is kept as an integer.  A sequence whose cells never
+//    rise above scB has running max
 //    max(0, scB + max over its residues of max_k (dbias - cost_k)), computed
 //    at its end from a per-residue table.
 #pragma once
@@ -48,6 +45,7 @@
 namespace hmsv {
 
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 constexpr uint32_t kMinus2 = 0xC000u;        // fp16 -2.0: score of dummy/padding slots
 constexpr int kBase = 190;
@@ -220,9 +218,31 @@ struct Lane {
     }
 };
 
-template <int G, int Q, bool MSV>
+// Kernel modes.
+enum Mode : int {
+    kSSV = 0,      // SSV (Alg. 7)
+    kMSV = 1,      // MSV (Alg. 2)
+};
+
+// Work-queue counter in the workspace.
+constexpr int kCtrMain = 0;      // next sequence of the range
+
+// One filter launch.  Every lane group pulls sequences (longest first)
+// from the call's range and runs their rows in blocks of four residues.
+//
+// MSV first runs a sequence with scB fixed at sat0(base - tjb - tbm).
+// Cells only grow with scB, and scB keeps that value until the running max
+// passes base + tec, so this result is exact when the running max stays at
+// or below base + tec (the J state never opens) or reaches the overflow
+// threshold.  Otherwise the group replays the sequence from its first row
+// in exact mode: after every row it checks (two instructions) whether any
+// cell passed the level at which scB would change or overflow occurs, and
+// only then runs Alg. 2's special-state update (group max, new scB, cells
+// lowered by the rise).  Waves without a group in exact mode skip the check.
+template <int G, int Q, int MODE>
 __global__ void __launch_bounds__(512)
 filter_kernel(KArgs a) {
+    constexpr bool MSV = MODE == kMSV;
     extern __shared__ uint32_t lds[];
     using L = Lane<G, Q, MSV>;
     constexpr int W = L::W;
@@ -255,17 +275,41 @@ filter_kernel(KArgs a) {
     int seq_rows = 0;
     int tjbm = 0;
     int xb = 0;                  // MSV: scB (integer filter units)
-    int cm = -1;                 // MSV: exact running max of earlier scB epochs
-    int built = -(1 << 30);      // MSV: running max scB was last computed from
+    int cm = -1;                 // MSV exact mode: exact running max of earlier scB epochs
+    int built = 0;               // MSV exact mode: running max scB was last computed from
+    uint32_t lvl = 0xffffffffu;  // MSV exact mode: check level (two u16 halves), all-ones = off
+    bool exact = false;          // MSV: group replays its sequence in exact mode
     bool ovf = false;
     bool active = false;
-    bool need = true;   // group wants a sequence
+    bool need = true;            // group wants a sequence
 
     // MSV running max = max(cm, current epoch's max + scB); -1 while the
     // current epoch never rose above scB.
     auto epoch_max = [&]() -> int {
         int m = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
         return m > 0 ? m + xb : -1;
+    };
+    // Exact mode: a cell above max(base + tec, built) moves scB; one at or
+    // above 255 - dbias overflows.  The check level is the larger relative
+    // cell value that does neither, as an fp16 pattern in both halves.
+    auto set_level = [&]() {
+        int lim = built > kBase + kTec ? built : kBase + kTec;
+        int top = 254 - dbias;
+        lim = lim < top ? lim : top;
+        int rel = lim - xb;
+        rel = rel < 0 ? 0 : rel;
+        lvl = (exact && !ovf) ? units_splat(rel) : 0xffffffffu;
+    };
+    auto start_sequence = [&]() {
+        off = seq_off;
+        rows_left = seq_rows;
+        xb = kBase - tjbm;
+        xb = xb < 0 ? 0 : xb;
+        st.reset();
+        cm = -1;
+        built = 0;
+        ovf = false;
+        set_level();
     };
 
     for (;;) {
@@ -275,142 +319,135 @@ filter_kernel(KArgs a) {
             int cnt = __popcll(m);
             int first = __ffsll((long long)m) - 1;
             uint32_t b = 0;
-            if (lane == first) b = atomicAdd(a.counter, (uint32_t)cnt);
+            if (lane == first) b = atomicAdd(a.counter + kCtrMain, (uint32_t)cnt);
             b = (uint32_t)__shfl((int)b, first);
             int rank = __popcll(m & ((1ull << lane) - 1ull));
-            int s = (int)b + rank;
-            s = __shfl(s, lane - j);
+            int q = (int)b + rank;
+            q = __shfl(q, lane - j);
             if (need) {
-                if (s < a.nseq) {
-                    SeqRec r = a.seqs[s];
-                    off = r.off;
-                    rows_left = (int)r.rows;
+                if (q < a.nseq) {
+                    SeqRec r = a.seqs[q];
+                    seq_off = r.off;
+                    seq_rows = (int)r.rows;
                     id = r.id;
                     tjbm = (int)r.tjb + a.tbm;
                     active = true;
                 } else {
-                    off = a.pad_off;
-                    rows_left = 0x7fffffff;
+                    seq_off = a.pad_off;
+                    seq_rows = 0x7fffffff;
                     active = false;
                 }
-                seq_off = off;
-                seq_rows = rows_left;
-                xb = kBase - tjbm;
-                xb = xb < 0 ? 0 : xb;
-                st.reset();
-                cm = -1;
-                built = -(1 << 30);
-                ovf = false;
+                exact = false;
+                start_sequence();
                 need = false;
             }
         }
         if (!__any(active)) break;
+        const bool wave_exact = MSV && __any(exact);
 
-        // ---- one tile of rows ------------------------------------------
-        uint32_t ckR[MSV ? Q : 1];
-        uint32_t ckE = st.xE;
-        const uint32_t ck_off = off;
-        if constexpr (MSV) {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) ckR[q] = st.R[q];
-        }
+        // ---- rows, four residues at a time, until some group ends --------
         const uint32_t step = active ? 4u : 0u;
-        int nb = 0;
         bool ended = false;
         uint32_t w = *(const uint32_t *)(a.res + off);
         do {
             uint32_t wn = *(const uint32_t *)(a.res + off + step);   // next 4 residues
-            st.row(T, w & 0xffu);
-            st.row(T, (w >> 8) & 0xffu);
-            st.row(T, (w >> 16) & 0xffu);
-            st.row(T, w >> 24);
+            if (!wave_exact) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) st.row(T, (w >> (8 * r)) & 0xffu);
+            } else if constexpr (MSV) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    st.row(T, (w >> (8 * r)) & 0xffu);
+                    // any cell above the level?  (saturating u16 subtract)
+                    bool hit = (uint32_t)__builtin_bit_cast(
+                        uint32_t, __builtin_elementwise_sub_sat(
+                            __builtin_bit_cast(u16x2, st.xE), __builtin_bit_cast(u16x2, lvl))) != 0u;
+                    if (__any(hit)) {
+                        // Alg. 2 special states after this row, for every group
+                        // whose running max passed its level (decided from the
+                        // group max, so all lanes of a group agree)
+                        int e2 = epoch_max();
+                        int m2 = cm > e2 ? cm : e2;
+                        int lim = built > kBase + kTec ? built : kBase + kTec;
+                        if (exact && !ovf && (m2 > lim || m2 >= 255 - dbias)) {
+                            if (m2 >= 255 - dbias) ovf = true;
+                            int j2 = m2 - kTec > kBase ? m2 - kTec : kBase;
+                            int xbn = j2 - tjbm;
+                            xbn = xbn < 0 ? 0 : (xbn > 255 ? 255 : xbn);
+                            if (xbn > xb) {          // new scB epoch
+                                st.lower(xbn - xb);
+                                st.xE = 0u;
+                                cm = m2;
+                                xb = xbn;
+                            }
+                            built = m2;
+                            set_level();
+                        }
+                    }
+                }
+            }
             // Consume the next word only here, so its load stays issued before
             // the four rows and its latency hides behind them.
             asm volatile("" : "+v"(wn));
             off += step;
             rows_left -= (int)step;
-            ++nb;
             ended = active && rows_left == 0;
             w = wn;
-        } while (nb < a.tile_blocks && !__any(ended));
-
-        if constexpr (MSV) {
-            // ---- special states: did scB move in this tile? -------------
-            int em = epoch_max();
-            int mx = cm > em ? cm : em;
-            int lim = built > kBase + kTec ? built : kBase + kTec;
-            bool trig = active && !ovf && (mx > lim || mx >= 255 - dbias);
-            if (__any(trig)) {
-#pragma unroll
-                for (int q = 0; q < Q; ++q) st.R[q] = ckR[q];
-                st.xE = ckE;
-                uint32_t o = ck_off;
-                for (int b = 0; b < nb; ++b) {
-                    uint32_t ww = *(const uint32_t *)(a.res + o);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        st.row(T, (ww >> (8 * r)) & 0xffu);
-                        int e2 = epoch_max();
-                        int m2 = cm > e2 ? cm : e2;
-                        if (m2 >= 255 - dbias) ovf = true;
-                        int j2 = m2 - kTec > kBase ? m2 - kTec : kBase;
-                        int xbn = j2 - tjbm;
-                        xbn = xbn < 0 ? 0 : (xbn > 255 ? 255 : xbn);
-                        if (xbn > xb) {          // new scB epoch
-                            st.lower(xbn - xb);
-                            st.xE = 0u;
-                            cm = m2;
-                            xb = xbn;
-                        }
-                        built = m2;
-                    }
-                    o += step;
-                }
-            }
-        }
+        } while (!__any(ended));
 
         // ---- finished sequences: record scores (Alg. 2 end-residue branch) -----
-        if (__any(ended)) {
-            int mx;
-            if constexpr (MSV) {
-                int em = epoch_max();
-                mx = cm > em ? cm : em;
-                // never above scB: max(0, scB + best score of its residues)
-                int bst = -(1 << 30);
-                if (ended && mx < 0) {
-                    for (int i = j; i < seq_rows; i += G) {
-                        int v = a.best[a.res[seq_off + i]];
-                        bst = v > bst ? v : bst;
-                    }
+        int mx;
+        if constexpr (MSV) {
+            int em = epoch_max();
+            mx = cm > em ? cm : em;
+            // never above scB: max(0, scB + best score of its residues)
+            int bst = -(1 << 30);
+            if (ended && mx < 0) {
+                for (int i = j; i < seq_rows; i += G) {
+                    int v = a.best[a.res[seq_off + i]];
+                    bst = v > bst ? v : bst;
                 }
-                bst = group_max<G>(bst);
-                if (mx < 0) {
-                    int v = xb + bst;
-                    mx = v > 0 ? v : 0;
-                }
-            } else {
-                mx = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
             }
-            if (ended && gstart) {
-                uint8_t sc, fl;
-                if constexpr (MSV) {
-                    bool of = ovf || mx >= 255 - dbias;
-                    int v = mx - kTec;
-                    sc = of ? 255 : (uint8_t)(v < 0 ? 0 : v);
-                    fl = of ? 1 : 0;
-                } else {
-                    bool of = mx >= 255;
-                    sc = of ? (uint8_t)127 : (uint8_t)(int8_t)(mx - 128);
-                    fl = of ? 1 : 0;
-                }
-                a.score[id] = sc;
-                a.flag[id] = fl;
+            bst = group_max<G>(bst);
+            if (mx < 0) {
+                int v = xb + bst;
+                mx = v > 0 ? v : 0;
             }
-            need = ended;
+        } else {
+            mx = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
         }
+        bool redo = false;
+        if constexpr (MSV) {
+            bool of = ovf || mx >= 255 - dbias;
+            // the J state may have opened: replay in exact mode
+            redo = ended && !exact && !of && mx > kBase + kTec;
+        }
+        if (ended && !redo && gstart) {
+            if constexpr (MODE == kSSV) {
+                bool of = mx >= 255;
+                a.score[id] = of ? (uint8_t)127 : (uint8_t)(int8_t)(mx - 128);
+                a.flag[id] = of ? 1 : 0;
+            } else {
+                bool of = ovf || mx >= 255 - dbias;
+                int v = mx - kTec;
+                a.score[id] = of ? 255 : (uint8_t)(v < 0 ? 0 : v);
+                a.flag[id] = of ? 1 : 0;
+            }
+        }
+        if constexpr (MSV) {
+            if (redo) {
+                exact = true;
+                start_sequence();
+            }
+        }
+        need = ended && !redo;
     }
 }
 
+// LDS image of the profile (see Layout): for table row x, register q and
+// lane j, the dword holds slots (q + 2jQ, q + (2j+1)Q) as two fp16 scores, in
+// every copy of q's chunk.  Threads 0..3 reset the work-queue counters.  For
+// MSV, kRows extra blocks compute best[x] = max_k (dbias - cost_k(x)).
 template <int G, int Q, bool MSV>
 __global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks) {
     using Lay = Layout<G, Q>;
@@ -435,10 +472,7 @@ __global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks) {
         return;
     }
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx == 0) {
-        a.counter[0] = 0u;
-        a.counter[1] = 0u;
-    }
+    if (idx < 4) a.counter[idx] = 0u;
     if (idx >= kRows * RS) return;
     int x = idx / RS;
     int rem = idx - x * RS;
@@ -464,30 +498,47 @@ __global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks) {
     a.image[idx] = slot_bits<MSV>(a, x, s0) | (slot_bits<MSV>(a, x, s0 + Q) << 16);
 }
 
+template <int G, int Q, int MODE>
+hipError_t launch_pass(const KArgs &a, int wpb, int blocks, hipStream_t s) {
+    size_t lds = lds_bytes(G, Q);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)filter_kernel<G, Q, MODE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((filter_kernel<G, Q, MODE>), dim3(blocks), dim3(wpb * 64), lds, s, a);
+    return hipGetLastError();
+}
+
+// prep (LDS image, counter, MSV best scores), then the filter kernel.
 template <int G, int Q, bool MSV>
 hipError_t launch_filter(const KArgs &a, int wpb, int blocks, hipStream_t s) {
+    constexpr int MODE = MSV ? kMSV : kSSV;
     constexpr int n = kRows * Layout<G, Q>::RS;
     constexpr int nb = (n + 255) / 256;
     hipLaunchKernelGGL((prep_kernel<G, Q, MSV>), dim3(nb + (MSV ? kRows : 0)), dim3(256), 0, s,
                        a, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     size_t lds = lds_bytes(G, Q);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)filter_kernel<G, Q, MSV>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        e = hipFuncSetAttribute((const void *)filter_kernel<G, Q, MODE>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((filter_kernel<G, Q, MSV>), dim3(blocks), dim3(wpb * 64), lds, s, a);
+    hipLaunchKernelGGL((filter_kernel<G, Q, MODE>), dim3(blocks), dim3(wpb * 64), lds, s, a);
     return hipGetLastError();
 }
 
 template <int G, int Q, bool MSV>
 int occupancy_filter(int wpb) {
+    constexpr int MODE = MSV ? kMSV : kSSV;
     int nb = 0;
     size_t lds = lds_bytes(G, Q);
-    if (hipFuncSetAttribute((const void *)filter_kernel<G, Q, MSV>,
+    if (hipFuncSetAttribute((const void *)filter_kernel<G, Q, MODE>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, filter_kernel<G, Q, MSV>, wpb * 64, lds)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, filter_kernel<G, Q, MODE>, wpb * 64, lds)
         != hipSuccess)
         return 0;
     return nb;

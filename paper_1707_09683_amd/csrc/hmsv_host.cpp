@@ -133,7 +133,6 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
     a.M = prof->M;
     a.dbias = prof->dbias;
     a.tbm = hmsv_tbm(prof->M);
-    a.tile_blocks = plan.tile / 4;
     a.res = db->d_res;
     a.seqs = db->d_seqs + first;
     a.nseq = (int32_t)count;
@@ -333,7 +332,10 @@ hmsv_status hmsv_default_plan(int32_t is_msv, int32_t M, hmsv_plan *plan) {
     return HMSV_ENOKERNEL;
 }
 
-size_t hmsv_workspace_bytes(void) { return kWsBytes; }
+size_t hmsv_workspace_bytes(int64_t nseq) {
+    (void)nseq;   // fixed today; the argument lets the layout grow with the database
+    return kWsBytes;
+}
 
 hmsv_status hmsv_msv_score(const hmsv_profile *prof, const hmsv_db *db, uint8_t *score,
                            uint8_t *flags, void *workspace, const hmsv_plan *plan,

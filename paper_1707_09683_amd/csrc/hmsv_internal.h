@@ -27,7 +27,6 @@ struct KArgs {
     int32_t M;
     int32_t dbias;
     int32_t tbm;
-    int32_t tile_blocks;   // rows per special-state check / 4
     const uint8_t *res;    // packed residues
     const SeqRec *seqs;    // already offset to the first record of the range
     int32_t nseq;          // records in the range

@@ -36,6 +36,40 @@ from . import Profile, Database, plan_for, score_range, workspace_bytes, quantiz
 from .autotune import lds_bytes
 
 
+def chunk_ranges(cum, nseq, M, chunk_cells):
+    """Split the processing order into ranges of about chunk_cells cells for
+    a profile of M nodes.  cum[t] = residues of the first t sequences of the
+    processing order.  Returns [(first, count), ...] covering 0..nseq."""
+    if not math.isfinite(chunk_cells) or cum is None or nseq == 0:
+        return [(0, nseq)]
+    per = max(1, int(chunk_cells // max(1, M)))            # residues per chunk
+    total = int(cum[-1])
+    k = max(1, int(math.ceil(total / per)))
+    cuts = np.searchsorted(cum, np.linspace(0, total, k + 1)[1:-1])
+    edges = [0] + sorted(set(int(c) for c in cuts if 0 < c < nseq)) + [nseq]
+    return [(a, b - a) for a, b in zip(edges[:-1], edges[1:])]
+
+
+def pick_next(active, running_lds, lds_budget, aging, rate):
+    """The admitted request whose next chunk goes to the GPU, or None.
+
+    active: requests with chunks left (attributes rid, t_arrival, remaining,
+    lds).  running_lds: {request id: LDS bytes} of requests with chunks on
+    the GPU.  A request is eligible if it already runs (its chunks stay in
+    order on its stream), if nothing runs, or if its LDS image fits beside
+    the running ones.  Among eligible requests the earliest
+    t_arrival + aging * remaining / rate wins (ties: lowest rid)."""
+    used = sum(running_lds.values())
+    cands = sorted(active, key=lambda r: (r.t_arrival + aging * r.remaining / rate, r.rid))
+    return next((c for c in cands if not running_lds or id(c) in running_lds
+                 or used + c.lds <= lds_budget), None)
+
+
+def slots_for_budget(hbm_budget, bytes_per_slot, max_inflight):
+    """Slots the HBM budget allows (at least one)."""
+    return max(1, min(max_inflight, int(hbm_budget // bytes_per_slot)))
+
+
 class Request:
     __slots__ = ("rid", "filt", "profile", "plan", "t_arrival", "t_admit", "t_done",
                  "future", "chunks", "next_chunk", "remaining", "slot", "event", "lds",
@@ -63,7 +97,7 @@ class _Slot:
     def __init__(self, n, device):
         self.score = torch.empty(n, dtype=torch.uint8, device=device)
         self.flags = torch.empty(n, dtype=torch.uint8, device=device)
-        self.ws = torch.zeros(workspace_bytes(), dtype=torch.uint8, device=device)
+        self.ws = torch.zeros(workspace_bytes(n), dtype=torch.uint8, device=device)
         self.h_score = torch.empty(n, dtype=torch.uint8, pin_memory=True)
         self.h_flags = torch.empty(n, dtype=torch.uint8, pin_memory=True)
         self.stream = torch.cuda.Stream(device)
@@ -71,7 +105,7 @@ class _Slot:
 
     @staticmethod
     def bytes_for(n):
-        return 2 * n + workspace_bytes()
+        return 2 * n + workspace_bytes(n)
 
 
 class Server:
@@ -82,8 +116,7 @@ class Server:
         self.bg = np.asarray(bg, dtype=np.float64)
         self.device = torch.device(device)
         n = db.nseq
-        fit = max(1, int(hbm_budget // _Slot.bytes_for(n)))
-        self.max_inflight = min(max_inflight, fit)
+        self.max_inflight = slots_for_budget(hbm_budget, _Slot.bytes_for(n), max_inflight)
         self.depth = depth
         self.chunk_cells = chunk_cells
         self.lds_budget = lds_budget
@@ -140,15 +173,7 @@ class Server:
 
     # ---- scheduler -----------------------------------------------------------
     def _chunks_for(self, M):
-        n = self.db.nseq
-        if not math.isfinite(self.chunk_cells) or self._cum is None:
-            return [(0, n)]
-        per = max(1, int(self.chunk_cells // M))           # residues per chunk
-        total = int(self._cum[-1])
-        k = max(1, int(math.ceil(total / per)))
-        cuts = np.searchsorted(self._cum, np.linspace(0, total, k + 1)[1:-1])
-        edges = [0] + sorted(set(int(c) for c in cuts if 0 < c < n)) + [n]
-        return [(a, b - a) for a, b in zip(edges[:-1], edges[1:])]
+        return chunk_ranges(self._cum, self.db.nseq, M, self.chunk_cells)
 
     def _admit(self):
         while self._queue:
@@ -175,11 +200,7 @@ class Server:
             # LDS of the distinct requests with chunks on the GPU (chunks of one
             # request run in order on its stream and never co-reside)
             running = {id(r): r.lds for r, _, _ in self._inflight}
-            used = sum(running.values())
-            cands = sorted(self._active, key=lambda r: (
-                r.t_arrival + self.aging * r.remaining / self.rate, r.rid))
-            r = next((c for c in cands if not running or id(c) in running
-                      or used + c.lds <= self.lds_budget), None)
+            r = pick_next(self._active, running, self.lds_budget, self.aging, self.rate)
             if r is None:
                 return
             ci = r.next_chunk

@@ -97,14 +97,21 @@ def test_lengths_and_implants(hm, filt, M):
         assert exp[1].sum() > 0          # overflow path exercised
 
 
-@pytest.mark.parametrize("tile", [4, 8, 64, 256])
-def test_msv_tile_sizes_agree(hm, tile):
-    rng = np.random.default_rng(77)
-    emis = synth.sample_emissions(rng, 130)
-    db = _implanted_db(rng, emis, 800, 1, 400, 0.15)
-    print(f"case msv tile={tile}", flush=True)
-    plan = hm.make_plan(8, 9, waves_per_block=4, tile=tile)
-    _assert_same(_gpu(hm, "msv", emis, db, plan), _oracle("msv", emis, db), what=f"tile {tile}")
+@pytest.mark.parametrize("M", [40, 130, 700])
+def test_msv_exact_replay_of_j_state_sequences(hm, M):
+    """A sequence first runs with scB fixed; one whose maximum lands between
+    base + tec and the overflow threshold is replayed in exact mode (scB
+    updated where the running max moves it).  Short implants make such
+    sequences common; their scores exceed base = 190."""
+    rng = np.random.default_rng(77 + M)
+    emis = synth.sample_emissions(rng, M)
+    db = synth.random_db(rng, 1500, 1, 400)
+    synth.implant(rng, db.res, db.offsets, [emis], 0.3)
+    print(f"case msv exact replay M={M}", flush=True)
+    exp = _oracle("msv", emis, db)
+    _assert_same(_gpu(hm, "msv", emis, db), exp, what=f"M={M}")
+    j_state = int(((exp[0] > 190) & (exp[1] == 0)).sum())
+    assert j_state > 5, j_state
 
 
 @pytest.mark.parametrize("filt", ["msv", "ssv"])
@@ -130,7 +137,7 @@ def test_repeated_calls_share_workspace(hm, cfg0):
     emis = cfg0.emissions[0]
     prof = hm.Profile.from_emissions(emis, synth.BG)
     gdb = hm.Database(cfg0.db.res, cfg0.db.offsets)
-    ws = hm.new_workspace()
+    ws = hm.new_workspace(nseq=gdb.nseq)
     outs = []
     for _ in range(3):
         s, f = hm.msv_score(prof, gdb, workspace=ws)

@@ -72,7 +72,7 @@ def test_range_calls_cover_database(env):
     full = hm.msv_score(prof, gdb)
     s = torch.zeros(gdb.nseq, dtype=torch.uint8, device="cuda")
     f = torch.zeros(gdb.nseq, dtype=torch.uint8, device="cuda")
-    ws = hm.new_workspace()
+    ws = hm.new_workspace(nseq=gdb.nseq)
     edges = [0, 1, 17, 1000, 3333, gdb.nseq]
     for a, b in zip(edges[:-1], edges[1:]):
         hm.score_range("msv", prof, gdb, a, b - a, s, f, ws)

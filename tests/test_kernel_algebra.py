@@ -17,7 +17,12 @@ I5  with scB fixed, the MSV cell update max(0, max(v, scB) + s) becomes one
     floored add on w = max(v, scB) - scB:  w' = max(w + s, 0).  When scB
     rises by d, every w becomes max(w - d, 0).  A row whose w are all 0 has
     maximum max(0, scB + max_k s_k(x)), so a sequence that never rises above
-    scB has running maximum max(0, scB + max over its residues of max_k s_k).
+    scB has running maximum max(0, scB + max over its residues of max_k s_k);
+I6  cell values only grow with scB, and scB stays at its start value until
+    the running maximum passes base + tec.  So one pass with scB fixed gives
+    the exact result when its running maximum stays <= base + tec or reaches
+    the overflow threshold; only sequences in between need the pass with
+    per-row scB updates.
 """
 import numpy as np
 
@@ -121,6 +126,65 @@ def model_msv_w(prof, x, tile=8, pad=4):
     if flag or c >= 255 - bias:
         return 255, 1
     return max(0, c - tec), 0
+
+
+def model_msv_two_pass(prof, x, pad=4):
+    """Pass 1 with scB fixed (I6, I5 cells); pass 2 (exact, per-row scB) only
+    for sequences whose fixed-scB maximum lies in (base + tec, 255 - dbias)."""
+    M, bias = prof["M"], prof["bias"]
+    s = bias - prof["cost"].astype(np.int64)
+    best = s.max(axis=1)
+    L = len(x)
+    rows = list(x) + [20] * ((-L) % pad if L else pad)
+    tjbm = q.tjb(L) + prof["tbm"]
+    tec, base = q.tec(), q.BASE
+    xb0 = max(0, base - tjbm)
+    Wc = np.zeros(M, np.int64)
+    run = 0
+    for r in rows:
+        Wc = np.maximum(0, np.concatenate(([0], Wc[:-1])) + s[r])
+        run = max(run, int(Wc.max()))
+    c = run + xb0 if run > 0 else max(0, xb0 + int(max(best[r] for r in rows)))
+    if c >= 255 - bias:
+        return (255, 1), "pass1"
+    if c <= base + tec:
+        return (max(0, c - tec), 0), "pass1"
+    # pass 2: exact, scB updated after every row, cells relative to scB
+    xb, cm, run, flag = xb0, -1, 0, False
+    Wc = np.zeros(M, np.int64)
+    for r in rows:
+        Wc = np.maximum(0, np.concatenate(([0], Wc[:-1])) + s[r])
+        run = max(run, int(Wc.max()))
+        c = max(cm, run + xb if run > 0 else -1)
+        if c >= 255 - bias:
+            flag = True
+        xbn = max(0, max(base, c - tec) - tjbm)
+        if xbn > xb:
+            Wc = np.maximum(0, Wc - (xbn - xb))
+            cm, run, xb = c, 0, xbn
+    c = max(cm, run + xb if run > 0 else -1)
+    if c < 0:
+        c = max(0, xb + int(max(best[r] for r in rows)))
+    if flag or c >= 255 - bias:
+        return (255, 1), "pass2"
+    return (max(0, c - tec), 0), "pass2"
+
+
+def test_msv_two_pass_matches_oracle():
+    rng = np.random.default_rng(24)
+    seen = {"pass1": 0, "pass2": 0}
+    for trial in range(40):
+        M = int(rng.choice([1, 3, 16, 48, 130]))
+        emis = synth.sample_emissions(rng, M)
+        prof = q.quantize(emis, synth.BG)
+        db = synth.random_db(rng, 12, 0, 200)
+        synth.implant(rng, db.res, db.offsets, [emis], 0.4)
+        for sidx in range(db.n):
+            x = db.seq(sidx)
+            got, how = model_msv_two_pass(prof, x)
+            assert got == oracle.msv_seq(prof, x), (trial, sidx, how)
+            seen[how] += 1
+    assert min(seen.values()) > 3, seen
 
 
 def model_ssv(prof, x, pad=4):
