@@ -94,8 +94,8 @@ typedef struct {
  * res:     host, concatenated residue codes (uint8, each < 32).
  * offsets: host, [nseq+1] int64, sequence i = res[offsets[i] .. offsets[i+1]).
  * Synchronous.  Fails with HMSV_EINVAL on null pointers, decreasing offsets
- * or codes >= 32; HMSV_EUNSUPPORTED if the packed size reaches 2^32 bytes or
- * nseq >= 2^31. */
+ * or codes >= 32; HMSV_EUNSUPPORTED if the packed size reaches 2^32 bytes,
+ * a sequence is longer than 2^24 - 4 residues, or nseq >= 2^31. */
 typedef struct hmsv_db hmsv_db;
 hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t nseq,
                            hmsv_db **out);
@@ -105,7 +105,7 @@ int64_t hmsv_db_residues(const hmsv_db *db);     /* real residues (no padding) *
 int64_t hmsv_db_padded_rows(const hmsv_db *db);  /* rows the kernels run */
 
 /* ---- launch plan --------------------------------------------------------
- * How one filter call maps onto the GPU.  A lane group of G lanes (4..64)
+ * How one filter call maps onto the GPU.  A lane group of G lanes (1..64)
  * aligns one sequence; each lane holds Q packed pairs of cells, so the
  * group covers 2*G*Q - 1 >= M nodes (one cell is a fixed -inf node).  64/G sequences share a wavefront (the
  * paper's multi-sequence alignment, Sec. 3.1 tier 4).  waves_per_block

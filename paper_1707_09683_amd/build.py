@@ -23,13 +23,17 @@ LIB = os.path.join(HERE, "libhmsv.so")
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# The atomic optimizer rewrites the work-queue atomic into a wave reduction
+# that reads its result back at once; the kernels defer that read to the
+# next sequence switch, so the rewrite is turned off.
 COMMON = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
           "-I", CSRC, "-I", INCLUDE, "-Wno-unused-command-line-argument"]
 
 # (G, largest Q).  The LDS table is 21 rows x G x Q dwords and must fit in
 # 160 KiB, which caps G = 64 at Q = 30 (profiles up to 3840 nodes).
-GROUPS = ((4, 32), (8, 32), (16, 32), (32, 32), (64, 30))
+GROUPS = ((1, 32), (2, 32), (4, 32), (8, 32), (16, 32), (32, 32), (64, 30))
 QCHUNK = 4
 
 

@@ -176,10 +176,14 @@ struct Lane {
     __device__ __forceinline__ void load_row(const uint32_t *TW, const uint32_t *T2,
                                              const uint32_t *T1, uint32_t x,
                                              uint32_t (&c)[Q]) {
-        const uint32_t rb = x * (uint32_t)RS;
+        // byte offset of row x: one multiply of the residue byte, no shift
+        const uint32_t rb = x * (uint32_t)(RS * 4);
+        auto at = [rb](const uint32_t *base) {
+            return (const uint32_t *)((const char *)base + rb);
+        };
 #pragma unroll
         for (int ch = 0; ch < Lay::NF; ++ch) {
-            const uint32_t *p = TW + rb + ch * Lay::CW;
+            const uint32_t *p = at(TW) + ch * Lay::CW;
             if constexpr (W == 4) {
                 uint4 v = *(const uint4 *)p;
                 c[ch * 4 + 0] = v.x; c[ch * 4 + 1] = v.y;
@@ -192,11 +196,11 @@ struct Lane {
             }
         }
         if constexpr (Lay::T2) {
-            uint2 v = *(const uint2 *)(T2 + rb);
+            uint2 v = *(const uint2 *)at(T2);
             c[Lay::Q2] = v.x;
             c[Lay::Q2 + 1] = v.y;
         }
-        if constexpr (Lay::T1) c[Lay::Q1] = T1[rb];
+        if constexpr (Lay::T1) c[Lay::Q1] = *at(T1);
     }
 
     // One residue row of Alg. 2 (MSV) / Alg. 7 (SSV): shift, fetch, cell update.
@@ -269,10 +273,9 @@ filter_kernel(KArgs a) {
 
     L st;
     uint32_t off = a.pad_off;
-    int rows_left = 0x7fffffff;
     uint32_t id = 0;
     uint32_t seq_off = 0;
-    int seq_rows = 0;
+    uint32_t seq_end = 0xffffffffu;   // offset just past the sequence's rows
     int tjbm = 0;
     int xb = 0;                  // MSV: scB (integer filter units)
     int cm = -1;                 // MSV exact mode: exact running max of earlier scB epochs
@@ -281,7 +284,53 @@ filter_kernel(KArgs a) {
     bool exact = false;          // MSV: group replays its sequence in exact mode
     bool ovf = false;
     bool active = false;
-    bool need = true;            // group wants a sequence
+    bool need = false;           // group wants a sequence
+    uint32_t w = 0;              // next four residues of the group's sequence
+
+    // Sequence pipeline (group-uniform).  While a group runs a sequence, the
+    // record of its next one (A, with A's first four residues stored in the
+    // record) is loaded and the queue position after that (qc) is claimed.
+    // At a switch: run A, load the record at qc as the new A, claim a new
+    // qc.  The record load and the claim's atomic issued at a switch are
+    // first used at a later one, so neither stalls the switch.  At every
+    // switch of the wavefront all lanes reload A (groups that keep theirs
+    // reload the same record), so the load is unconditional and its result
+    // lands in place without a wait.  A claim's atomic result stays in the
+    // lane that issued it (pend_b, in lane pend_first) until the next switch
+    // of the wavefront resolves it.
+    //
+    // Queue positions map to records so that the grid's N groups start on
+    // the N longest sequences and each holds two of the shortest as A and
+    // qc: positions [0, N) are records [0, N), positions [N, 3N) the last
+    // 2N records (shortest first from the end), positions from 3N (claimed
+    // dynamically) the records in between, longest first.  No group thus
+    // queues a long sequence behind its first one.  Ranges with fewer than
+    // 3N records use positions as record numbers.
+    const uint4 *recs = (const uint4 *)a.seqs;
+    const int nseq = a.nseq;                      // ranges are never empty
+    const int ngroups = (int)(gridDim.x * (blockDim.x / G));
+    const int gid = (int)(blockIdx.x * (blockDim.x / G) + threadIdx.x / G);
+    const bool tail = nseq >= 3 * ngroups;
+    constexpr int kNone = 0x7fffffff;             // position past the range
+    auto record_of = [&](int p) -> int {          // queue position -> record
+        if (p >= nseq) return kNone;
+        if (!tail || p < ngroups) return p;
+        if (p < 3 * ngroups) return nseq - 1 - (p - ngroups);
+        return p - 2 * ngroups;
+    };
+    auto fetch = [&](int r) -> uint4 { return recs[r < nseq ? r : nseq - 1]; };
+    uint4 ra;                    // record A: off, rows | tjb << 24, id, first word
+    int qa, qc;                  // records of A and of the claimed position (kNone: none)
+    uint32_t pend_b = 0;
+    int pend_first = -1;         // wave-uniform
+    auto start_record = [&](const uint4 &r, bool valid) {
+        active = valid;
+        seq_off = valid ? r.x : a.pad_off;
+        seq_end = valid ? r.x + (r.y & kRowsMask) : 0xffffffffu;
+        id = r.z;
+        tjbm = (int)(r.y >> 24) + a.tbm;
+        w = r.w;
+    };
 
     // MSV running max = max(cm, current epoch's max + scB); -1 while the
     // current epoch never rose above scB.
@@ -302,7 +351,6 @@ filter_kernel(KArgs a) {
     };
     auto start_sequence = [&]() {
         off = seq_off;
-        rows_left = seq_rows;
         xb = kBase - tjbm;
         xb = xb < 0 ? 0 : xb;
         st.reset();
@@ -312,35 +360,42 @@ filter_kernel(KArgs a) {
         set_level();
     };
 
+    {
+        int q0 = record_of(gid);
+        uint4 r0 = fetch(q0);
+        qa = record_of(ngroups + gid);
+        ra = fetch(qa);
+        qc = record_of(2 * ngroups + gid);
+        start_record(r0, q0 != kNone);
+        exact = false;
+        start_sequence();
+    }
+
     for (;;) {
         // ---- hand sequences to groups that need one (uniform) ----------
         if (__any(need)) {
-            unsigned long long m = __ballot(need && gstart);
-            int cnt = __popcll(m);
-            int first = __ffsll((long long)m) - 1;
-            uint32_t b = 0;
-            if (lane == first) b = atomicAdd(a.counter + kCtrMain, (uint32_t)cnt);
-            b = (uint32_t)__shfl((int)b, first);
-            int rank = __popcll(m & ((1ull << lane) - 1ull));
-            int q = (int)b + rank;
-            q = __shfl(q, lane - j);
+            // resolve the previous claim (its atomic has long returned); a
+            // group with a pending claim holds -1 - its rank in qc
+            if (pend_first >= 0) {
+                int b = __shfl((int)pend_b, pend_first);
+                if (qc < 0) qc = record_of(3 * ngroups + b - 1 - qc);
+            }
             if (need) {
-                if (q < a.nseq) {
-                    SeqRec r = a.seqs[q];
-                    seq_off = r.off;
-                    seq_rows = (int)r.rows;
-                    id = r.id;
-                    tjbm = (int)r.tjb + a.tbm;
-                    active = true;
-                } else {
-                    seq_off = a.pad_off;
-                    seq_rows = 0x7fffffff;
-                    active = false;
-                }
+                start_record(ra, qa != kNone);
+                qa = qc;
                 exact = false;
                 start_sequence();
-                need = false;
             }
+            ra = fetch(qa);
+            // new claims for the groups that just switched
+            unsigned long long m = __ballot(need && gstart);
+            int first = __ffsll((long long)m) - 1;
+            if (lane == first) pend_b = atomicAdd(a.counter + kCtrMain, (uint32_t)__popcll(m));
+            pend_first = first;
+            int rank = __popcll(m & ((1ull << lane) - 1ull));
+            rank = __shfl(rank, lane - j);
+            if (need) qc = -1 - rank;
+            need = false;
         }
         if (!__any(active)) break;
         const bool wave_exact = MSV && __any(exact);
@@ -348,9 +403,9 @@ filter_kernel(KArgs a) {
         // ---- rows, four residues at a time, until some group ends --------
         const uint32_t step = active ? 4u : 0u;
         bool ended = false;
-        uint32_t w = *(const uint32_t *)(a.res + off);
         do {
-            uint32_t wn = *(const uint32_t *)(a.res + off + step);   // next 4 residues
+            const uint32_t offn = off + step;
+            uint32_t wn = *(const uint32_t *)(a.res + offn);         // next 4 residues
             if (!wave_exact) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) st.row(T, (w >> (8 * r)) & 0xffu);
@@ -389,9 +444,8 @@ filter_kernel(KArgs a) {
             // Consume the next word only here, so its load stays issued before
             // the four rows and its latency hides behind them.
             asm volatile("" : "+v"(wn));
-            off += step;
-            rows_left -= (int)step;
-            ended = active && rows_left == 0;
+            off = offn;
+            ended = off == seq_end;
             w = wn;
         } while (!__any(ended));
 
@@ -403,8 +457,8 @@ filter_kernel(KArgs a) {
             // never above scB: max(0, scB + best score of its residues)
             int bst = -(1 << 30);
             if (ended && mx < 0) {
-                for (int i = j; i < seq_rows; i += G) {
-                    int v = a.best[a.res[seq_off + i]];
+                for (uint32_t p = seq_off + j; p < seq_end; p += G) {
+                    int v = a.best[a.res[p]];
                     bst = v > bst ? v : bst;
                 }
             }
@@ -438,6 +492,7 @@ filter_kernel(KArgs a) {
             if (redo) {
                 exact = true;
                 start_sequence();
+                w = *(const uint32_t *)(a.res + seq_off);
             }
         }
         need = ended && !redo;
@@ -496,18 +551,6 @@ __global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks) {
     int qq = q0 + (rem - jj * w);
     int s0 = qq + Q * (2 * jj);
     a.image[idx] = slot_bits<MSV>(a, x, s0) | (slot_bits<MSV>(a, x, s0 + Q) << 16);
-}
-
-template <int G, int Q, int MODE>
-hipError_t launch_pass(const KArgs &a, int wpb, int blocks, hipStream_t s) {
-    size_t lds = lds_bytes(G, Q);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)filter_kernel<G, Q, MODE>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((filter_kernel<G, Q, MODE>), dim3(blocks), dim3(wpb * 64), lds, s, a);
-    return hipGetLastError();
 }
 
 // prep (LDS image, counter, MSV best scores), then the filter kernel.

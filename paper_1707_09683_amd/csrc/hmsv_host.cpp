@@ -252,10 +252,10 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
     for (int64_t t = 0; t < nseq; ++t) {
         int64_t i = order[t];
         uint64_t r = (uint64_t)std::max<int64_t>(4, (len[i] + 3) & ~(int64_t)3);
+        if (r >= kRowsLimit) return HMSV_EUNSUPPORTED;
         recs[t].off = (uint32_t)total;
-        recs[t].rows = (uint32_t)r;
+        recs[t].rt = (uint32_t)r | ((uint32_t)hmsv_tjb(len[i]) << 24);
         recs[t].id = (uint32_t)i;
-        recs[t].tjb = (uint32_t)hmsv_tjb(len[i]);
 
         total += r;
         rows += r;
@@ -269,6 +269,7 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
         const uint8_t *p = res + offsets[i];
         uint8_t *d = packed.data() + recs[t].off;
         for (int64_t k = 0; k < len[i]; ++k) d[k] = p[k] < HMSV_K ? p[k] : kInvalidCode;
+        std::memcpy(&recs[t].first, d, sizeof(uint32_t));
     }
     hmsv_db *db = new (std::nothrow) hmsv_db;
     if (!db) return HMSV_ENOMEM;
@@ -317,7 +318,7 @@ hmsv_status hmsv_default_plan(int32_t is_msv, int32_t M, hmsv_plan *plan) {
     // Narrowest lane group whose registers (Q <= 32 per lane) still hold the
     // profile: more sequences per wavefront and more cells per row of
     // per-row overhead (measured best at M = 48, 400 and 2400).
-    for (int G : {4, 8, 16, 32, 64}) {
+    for (int G : {1, 2, 4, 8, 16, 32, 64}) {
         int Q = (M + 1 + 2 * G - 1) / (2 * G);
         if (Q > 32 || lds_bytes(G, Q) > (size_t)kLdsBytes) continue;
         if (!registry().find(is_msv, G, Q)) continue;

@@ -16,10 +16,14 @@ constexpr int kLdsBytes = 160 * 1024;
 // One database sequence in processing order (longest first).
 struct SeqRec {
     uint32_t off;    // byte offset of its first residue in the packed stream
-    uint32_t rows;   // rows to run: length rounded up to a multiple of 4, at least 4
+    uint32_t rt;     // rows | tjb << 24: rows to run (length rounded up to a
+                     // multiple of 4, at least 4, below kRowsLimit) and the
+                     // length-model cost tjb(L) of its true length (< 256)
     uint32_t id;     // index in the caller's original order
-    uint32_t tjb;    // length-model cost tjb(L) of its true length
+    uint32_t first;  // its first four residues (the packed stream's bytes at off)
 };
+constexpr uint32_t kRowsMask = 0xffffffu;
+constexpr uint32_t kRowsLimit = 0xffffffu;    // rows must stay below
 
 struct KArgs {
     const uint8_t *cost;   // [32][M] MSV costs (device)

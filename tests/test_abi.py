@@ -80,6 +80,11 @@ def test_db_create_validates_on_host():
     assert hm._lib.hmsv_db_create(hm._np_ptr(res), hm._np_ptr(off), 2, ctypes.byref(h)) == -1
     assert hm._lib.hmsv_db_create(hm._np_ptr(res), None, 2, ctypes.byref(h)) == -1
     assert hm._lib.hmsv_db_create(hm._np_ptr(res), hm._np_ptr(off), 2, None) == -1
+    # a sequence longer than 2^24 - 4 residues does not fit a record's row field
+    big = np.zeros((1 << 24) - 3, np.uint8)
+    off = np.array([0, 0, big.size], np.int64)
+    assert hm._lib.hmsv_db_create(hm._np_ptr(big), hm._np_ptr(off), 2, ctypes.byref(h)) == -2
+    assert not h.value
 
 
 def test_score_rejects_bad_arguments_before_launch():

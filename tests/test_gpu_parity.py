@@ -59,7 +59,7 @@ def test_m48_2k_default_plan(hm, cfg0, filt):
     _assert_same(_gpu(hm, filt, emis, cfg0.db), _oracle(filt, emis, cfg0.db), what=filt)
 
 
-PLANS_M48 = [(4, 7), (4, 8), (8, 4), (8, 5), (16, 2), (32, 1), (64, 1)]
+PLANS_M48 = [(1, 25), (1, 32), (2, 13), (2, 14), (4, 7), (4, 8), (8, 4), (8, 5), (16, 2), (32, 1), (64, 1)]
 
 
 @pytest.mark.parametrize("filt", ["msv", "ssv"])
