@@ -231,6 +231,15 @@ enum Mode : int {
 // Work-queue counter in the workspace.
 constexpr int kCtrMain = 0;      // next sequence of the range
 
+// Sequence ends a wavefront collects before it leaves the row loop to
+// record scores and hand out sequences (see filter_kernel).
+template <int G>
+constexpr int kExitGroups = G == 1 ? 8 : G == 2 ? 4 : G == 4 ? 2 : 1;
+
+// Residue words (four residues each) per load and lane.
+template <int G>
+constexpr int kWordsPerLoad = G <= 4 ? 4 : 1;
+
 // One filter launch.  Every lane group pulls sequences (longest first)
 // from the call's range and runs their rows in blocks of four residues.
 //
@@ -285,7 +294,15 @@ filter_kernel(KArgs a) {
     bool ovf = false;
     bool active = false;
     bool need = false;           // group wants a sequence
-    uint32_t w = 0;              // next four residues of the group's sequence
+    // Residues come in words of four, K words per load: narrow groups (up
+    // to 32 sequences per wavefront, each streaming its own bytes) load 16
+    // residues per lane so each load is issued 16 rows before its first use;
+    // their sequences are then run in whole 16-row steps (the extra rows
+    // are non-scoring padding, which cannot change a score).
+    constexpr int K = kWordsPerLoad<G>;
+    uint32_t wv[K];              // next 4K residues of the group's sequence
+#pragma unroll
+    for (int k = 0; k < K; ++k) wv[k] = 0u;
 
     // Sequence pipeline (group-uniform).  While a group runs a sequence, the
     // record of its next one (A, with A's first four residues stored in the
@@ -318,18 +335,38 @@ filter_kernel(KArgs a) {
         if (p < 3 * ngroups) return nseq - 1 - (p - ngroups);
         return p - 2 * ngroups;
     };
-    auto fetch = [&](int r) -> uint4 { return recs[r < nseq ? r : nseq - 1]; };
+    auto fetch = [&](int r, uint4 &h, uint4 &f) {
+        const uint4 *p = recs + 2 * (r < nseq ? r : nseq - 1);
+        h = p[0];
+        if constexpr (K == 4) f = p[1];
+    };
     uint4 ra;                    // record A: off, rows | tjb << 24, id, first word
+    uint4 ra16;                  // record A's first sixteen residues (K = 4)
     int qa, qc;                  // records of A and of the claimed position (kNone: none)
     uint32_t pend_b = 0;
     int pend_first = -1;         // wave-uniform
-    auto start_record = [&](const uint4 &r, bool valid) {
+    auto start_record = [&](const uint4 &r, const uint4 &r16, bool valid) {
         active = valid;
+        uint32_t rows = r.y & kRowsMask;
+        if constexpr (K == 4) rows = (rows + 15u) & ~15u;
         seq_off = valid ? r.x : a.pad_off;
-        seq_end = valid ? r.x + (r.y & kRowsMask) : 0xffffffffu;
+        seq_end = valid ? r.x + rows : a.pad_off;
         id = r.z;
         tjbm = (int)(r.y >> 24) + a.tbm;
-        w = r.w;
+        if constexpr (K == 4) {
+            wv[0] = r16.x; wv[1] = r16.y; wv[2] = r16.z; wv[3] = r16.w;
+        } else {
+            wv[0] = r.w;
+        }
+    };
+    // the residue words at offset o
+    auto load_words = [&](uint32_t o, uint32_t (&d)[K]) {
+        if constexpr (K == 4) {
+            uint4 v = *(const uint4 *)(a.res + o);
+            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        } else {
+            d[0] = *(const uint32_t *)(a.res + o);
+        }
     };
 
     // MSV running max = max(cm, current epoch's max + scB); -1 while the
@@ -362,11 +399,12 @@ filter_kernel(KArgs a) {
 
     {
         int q0 = record_of(gid);
-        uint4 r0 = fetch(q0);
+        uint4 r0, r016;
+        fetch(q0, r0, r016);
         qa = record_of(ngroups + gid);
-        ra = fetch(qa);
+        fetch(qa, ra, ra16);
         qc = record_of(2 * ngroups + gid);
-        start_record(r0, q0 != kNone);
+        start_record(r0, r016, q0 != kNone);
         exact = false;
         start_sequence();
     }
@@ -381,12 +419,12 @@ filter_kernel(KArgs a) {
                 if (qc < 0) qc = record_of(3 * ngroups + b - 1 - qc);
             }
             if (need) {
-                start_record(ra, qa != kNone);
+                start_record(ra, ra16, qa != kNone);
                 qa = qc;
                 exact = false;
                 start_sequence();
             }
-            ra = fetch(qa);
+            fetch(qa, ra, ra16);
             // new claims for the groups that just switched
             unsigned long long m = __ballot(need && gstart);
             int first = __ffsll((long long)m) - 1;
@@ -400,19 +438,29 @@ filter_kernel(KArgs a) {
         if (!__any(active)) break;
         const bool wave_exact = MSV && __any(exact);
 
-        // ---- rows, four residues at a time, until some group ends --------
-        const uint32_t step = active ? 4u : 0u;
+        // ---- rows, four residues at a time --------------------------------
+        // A group that reaches its end stays there: its offset stops at the
+        // end, where a word of non-scoring residues follows every sequence,
+        // so its cells fall to zero and its running max is kept.  The rows
+        // continue until kExitGroups<G> groups of the wavefront have ended
+        // (all of them if fewer are active), so narrow groups pay for the
+        // switch code once per several sequence ends.
+        const int n_act = __popcll(__ballot(active && gstart));
+        const int e_min = n_act < kExitGroups<G> ? n_act : kExitGroups<G>;
+        const uint32_t step = active ? 4u * K : 0u;
         bool ended = false;
         do {
-            const uint32_t offn = off + step;
-            uint32_t wn = *(const uint32_t *)(a.res + offn);         // next 4 residues
+            uint32_t offn = off + step;
+            if constexpr (kExitGroups<G> > 1) offn = offn < seq_end ? offn : seq_end;
+            uint32_t wn[K];
+            load_words(offn, wn);                                    // next 4K residues
             if (!wave_exact) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) st.row(T, (w >> (8 * r)) & 0xffu);
+                for (int r = 0; r < 4 * K; ++r) st.row(T, (wv[r / 4] >> (8 * (r % 4))) & 0xffu);
             } else if constexpr (MSV) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    st.row(T, (w >> (8 * r)) & 0xffu);
+                for (int r = 0; r < 4 * K; ++r) {
+                    st.row(T, (wv[r / 4] >> (8 * (r % 4))) & 0xffu);
                     // any cell above the level?  (saturating u16 subtract)
                     bool hit = (uint32_t)__builtin_bit_cast(
                         uint32_t, __builtin_elementwise_sub_sat(
@@ -443,11 +491,13 @@ filter_kernel(KArgs a) {
             }
             // Consume the next word only here, so its load stays issued before
             // the four rows and its latency hides behind them.
-            asm volatile("" : "+v"(wn));
+#pragma unroll
+            for (int k = 0; k < K; ++k) asm volatile("" : "+v"(wn[k]));
             off = offn;
-            ended = off == seq_end;
-            w = wn;
-        } while (!__any(ended));
+            ended = active && off == seq_end;
+#pragma unroll
+            for (int k = 0; k < K; ++k) wv[k] = wn[k];
+        } while (__popcll(__ballot(ended && gstart)) < e_min);
 
         // ---- finished sequences: record scores (Alg. 2 end-residue branch) -----
         int mx;
@@ -492,7 +542,7 @@ filter_kernel(KArgs a) {
             if (redo) {
                 exact = true;
                 start_sequence();
-                w = *(const uint32_t *)(a.res + seq_off);
+                load_words(seq_off, wv);
             }
         }
         need = ended && !redo;

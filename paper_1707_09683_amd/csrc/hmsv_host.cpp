@@ -257,7 +257,9 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
         recs[t].rt = (uint32_t)r | ((uint32_t)hmsv_tjb(len[i]) << 24);
         recs[t].id = (uint32_t)i;
 
-        total += r;
+        // 16-byte aligned; the rows rounded up to 16, then 16 bytes of code 20
+        // (narrow lane groups run 16 rows per step and read past the end)
+        total += ((r + 15) & ~(uint64_t)15) + 16;
         rows += r;
         if (total >= ((uint64_t)1 << 32) - 64) return HMSV_EUNSUPPORTED;
     }
@@ -270,6 +272,7 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
         uint8_t *d = packed.data() + recs[t].off;
         for (int64_t k = 0; k < len[i]; ++k) d[k] = p[k] < HMSV_K ? p[k] : kInvalidCode;
         std::memcpy(&recs[t].first, d, sizeof(uint32_t));
+        std::memcpy(recs[t].first16, d, 4 * sizeof(uint32_t));
     }
     hmsv_db *db = new (std::nothrow) hmsv_db;
     if (!db) return HMSV_ENOMEM;

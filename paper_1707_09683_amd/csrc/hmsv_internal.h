@@ -15,13 +15,15 @@ constexpr int kLdsBytes = 160 * 1024;
 
 // One database sequence in processing order (longest first).
 struct SeqRec {
-    uint32_t off;    // byte offset of its first residue in the packed stream
-    uint32_t rt;     // rows | tjb << 24: rows to run (length rounded up to a
-                     // multiple of 4, at least 4, below kRowsLimit) and the
-                     // length-model cost tjb(L) of its true length (< 256)
-    uint32_t id;     // index in the caller's original order
-    uint32_t first;  // its first four residues (the packed stream's bytes at off)
+    uint32_t off;       // byte offset of its first residue (16-byte aligned)
+    uint32_t rt;        // rows | tjb << 24: rows to run (length rounded up to a
+                        // multiple of 4, at least 4, below kRowsLimit) and the
+                        // length-model cost tjb(L) of its true length (< 256)
+    uint32_t id;        // index in the caller's original order
+    uint32_t first;     // its first four residues
+    uint32_t first16[4];  // its first sixteen residues
 };
+static_assert(sizeof(SeqRec) == 32, "records are two 16-byte loads");
 constexpr uint32_t kRowsMask = 0xffffffu;
 constexpr uint32_t kRowsLimit = 0xffffffu;    // rows must stay below
 
