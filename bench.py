@@ -51,18 +51,27 @@ INSTR_PER_CELL = {"msv": 0.75, "ssv": 0.75}
 # HBM bytes per dispatch of the headline kernel come from rocprofv3
 # FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB device copy measured the same
 # way (profiles/traffic_*.json).  A record is used only if it was taken on
-# the current kernel source and the same plan and workload.
+# the current library sources (kernel and database layout) and the same plan
+# and workload.
 PROFILES = os.path.join(ROOT, "profiles")
+
+
+def library_source_sha1():
+    import glob
+    import hashlib
+    h = hashlib.sha1()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1707_09683_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def traffic_for(workload, plan):
     import glob
-    import hashlib
-    src = os.path.join(ROOT, "paper_1707_09683_amd", "csrc", "filter_kernel.hpp")
-    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    sha = library_source_sha1()
     for f in glob.glob(os.path.join(PROFILES, "traffic_*.json")):
         rec = json.load(open(f))
-        if rec.get("kernel_source_sha1") == sha and rec.get("workload") == workload \
+        if rec.get("library_source_sha1") == sha and rec.get("workload") == workload \
                 and list(rec.get("plan", [])) == list(plan):
             return rec["bytes_per_launch"]
     return None
