@@ -123,6 +123,13 @@ typedef struct {
 /* The library's default plan for a filter ("msv" = 1, "ssv" = 0) and M. */
 hmsv_status hmsv_default_plan(int32_t is_msv, int32_t M, hmsv_plan *plan);
 
+/* Bytes of LDS a plan's kernels hold per workgroup (the profile's image in
+ * the kernel's layout, the same for both filters), or 0 if G is not a power
+ * of two in 1..64 or Q < 1.  Plans above 160 KiB are rejected by the
+ * scoring calls (HMSV_EUNSUPPORTED); a scheduler can add the figures of
+ * kernels it wants to co-reside on one CU. */
+size_t hmsv_plan_lds_bytes(int32_t G, int32_t Q);
+
 /* Device workspace needed by a scoring call on a database of nseq
  * sequences (bytes): the work-queue counters, the MSV per-residue best
  * scores and the profile converted to the kernel's LDS layout. */

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libhmsv.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
-                      "`python -m paper_1707_09683_amd.build` (hipcc, gfx950)")
+                      "`python paper_1707_09683_amd/build.py` (hipcc, gfx950)")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -82,6 +82,8 @@ _lib.hmsv_default_plan.restype = ctypes.c_int
 _lib.hmsv_default_plan.argtypes = [_i32, _i32, ctypes.POINTER(Plan)]
 _lib.hmsv_workspace_bytes.restype = ctypes.c_size_t
 _lib.hmsv_workspace_bytes.argtypes = [_i64]
+_lib.hmsv_plan_lds_bytes.restype = ctypes.c_size_t
+_lib.hmsv_plan_lds_bytes.argtypes = [_i32, _i32]
 for _f in ("hmsv_msv_score", "hmsv_ssv_score"):
     getattr(_lib, _f).restype = ctypes.c_int
     getattr(_lib, _f).argtypes = [ctypes.POINTER(_CProfile), _P, _P, _P, _P,
@@ -95,7 +97,8 @@ _lib.hmsv_db_order.argtypes = [_P, _P]
 
 EXPORTED = ("hmsv_strerror", "hmsv_tbm", "hmsv_tjb", "hmsv_quantize", "hmsv_db_create",
             "hmsv_db_destroy", "hmsv_db_nseq", "hmsv_db_residues", "hmsv_db_padded_rows",
-            "hmsv_default_plan", "hmsv_workspace_bytes", "hmsv_msv_score", "hmsv_ssv_score",
+            "hmsv_default_plan", "hmsv_plan_lds_bytes", "hmsv_workspace_bytes",
+            "hmsv_msv_score", "hmsv_ssv_score",
             "hmsv_batch_create", "hmsv_batch_launch", "hmsv_batch_destroy",
             "hmsv_msv_score_range", "hmsv_ssv_score_range", "hmsv_db_order")
 
@@ -218,6 +221,11 @@ def plan_for(filt: str, M: int) -> Plan:
     table, key = _tuned
     t = autotune.lookup(table, key, filt, int(M)) if key else None
     return make_plan(*t) if t else default_plan(filt, M)
+
+
+def plan_lds_bytes(G, Q) -> int:
+    """LDS bytes per workgroup of a plan's kernels (0 for an invalid shape)."""
+    return int(_lib.hmsv_plan_lds_bytes(int(G), int(Q)))
 
 
 def workspace_bytes(nseq: int) -> int:

@@ -30,15 +30,9 @@ LDS_LIMIT = 160 * 1024
 
 
 def lds_bytes(G, Q):
-    """Bytes of a plan's LDS image (mirrors lds_bytes in the library)."""
-    W = 64 // G if G >= 16 else 4
-
-    def copies(w):
-        return max(1, 64 // (G * w))
-    nf, r = divmod(Q, W)
-    rs = nf * copies(W) * G * W + (copies(2) * G * 2 if r & 2 else 0) + \
-        (copies(1) * G if r & 1 else 0)
-    return 21 * rs * 4
+    """Bytes of a plan's LDS image, as the library computes it."""
+    from . import plan_lds_bytes
+    return plan_lds_bytes(G, Q)
 
 
 def q_for(G, M):

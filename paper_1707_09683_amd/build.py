@@ -2,7 +2,8 @@
 
 The kernel template is compiled once per (group width G, range of Q) so the
 instantiations build in parallel; the host code is one more translation
-unit.  Usage: ``python -m paper_1707_09683_amd.build [--jobs N] [--incremental]``.
+unit.  Usage: ``python paper_1707_09683_amd/build.py [--jobs N] [--incremental]``
+(run as a file: importing the package needs the library this script builds).
 """
 from __future__ import annotations
 

@@ -65,8 +65,11 @@ constexpr int read_width() { return G >= 16 ? 64 / G : 4; }
 template <int G, int Q>
 struct Layout {
     static constexpr int W = read_width<G>();
-    static constexpr int NF = Q / W;                  // full chunks
-    static constexpr int R = Q - NF * W;              // tail dwords (0..W-1)
+    // With 4-dword chunks a partial last chunk is read whole (its unused
+    // dwords are padding): one LDS address per row serves every read.
+    static constexpr bool WIDE_TAIL = W == 4 && Q % 4 != 0;
+    static constexpr int NF = WIDE_TAIL ? Q / W + 1 : Q / W;   // chunks of W dwords
+    static constexpr int R = WIDE_TAIL ? 0 : Q - NF * W;      // tail dwords (0..W-1)
     static constexpr bool T2 = (R & 2) != 0;
     static constexpr bool T1 = (R & 1) != 0;
     static constexpr int copies(int w) { return 64 / (G * w) > 1 ? 64 / (G * w) : 1; }
@@ -186,8 +189,10 @@ struct Lane {
             const uint32_t *p = at(TW) + ch * Lay::CW;
             if constexpr (W == 4) {
                 uint4 v = *(const uint4 *)p;
-                c[ch * 4 + 0] = v.x; c[ch * 4 + 1] = v.y;
-                c[ch * 4 + 2] = v.z; c[ch * 4 + 3] = v.w;
+                if (ch * 4 + 0 < Q) c[ch * 4 + 0] = v.x;
+                if (ch * 4 + 1 < Q) c[ch * 4 + 1] = v.y;
+                if (ch * 4 + 2 < Q) c[ch * 4 + 2] = v.z;
+                if (ch * 4 + 3 < Q) c[ch * 4 + 3] = v.w;
             } else if constexpr (W == 2) {
                 uint2 v = *(const uint2 *)p;
                 c[ch * 2 + 0] = v.x; c[ch * 2 + 1] = v.y;
@@ -600,7 +605,8 @@ __global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks) {
     int jj = rem / w;
     int qq = q0 + (rem - jj * w);
     int s0 = qq + Q * (2 * jj);
-    a.image[idx] = slot_bits<MSV>(a, x, s0) | (slot_bits<MSV>(a, x, s0 + Q) << 16);
+    a.image[idx] = qq >= Q ? 0u                    // padding of a partial chunk
+                           : slot_bits<MSV>(a, x, s0) | (slot_bits<MSV>(a, x, s0 + Q) << 16);
 }
 
 // prep (LDS image, counter, MSV best scores), then the filter kernel.

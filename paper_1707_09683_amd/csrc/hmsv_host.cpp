@@ -336,6 +336,11 @@ hmsv_status hmsv_default_plan(int32_t is_msv, int32_t M, hmsv_plan *plan) {
     return HMSV_ENOKERNEL;
 }
 
+size_t hmsv_plan_lds_bytes(int32_t G, int32_t Q) {
+    if (G < 1 || G > 64 || (64 % G) != 0 || Q < 1) return 0;
+    return lds_bytes(G, Q);
+}
+
 size_t hmsv_workspace_bytes(int64_t nseq) {
     (void)nseq;   // fixed today; the argument lets the layout grow with the database
     return kWsBytes;

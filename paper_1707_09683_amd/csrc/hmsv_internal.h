@@ -67,6 +67,7 @@ inline size_t lds_bytes(int G, int Q) {
     int W = G >= 16 ? 64 / G : 4;
     auto copies = [G](int w) { return 64 / (G * w) > 1 ? 64 / (G * w) : 1; };
     int nf = Q / W, r = Q - nf * W;
+    if (W == 4 && r != 0) { nf += 1; r = 0; }    // partial last chunk read whole
     size_t rs = (size_t)nf * copies(W) * G * W + ((r & 2) ? (size_t)copies(2) * G * 2 : 0) +
                 ((r & 1) ? (size_t)copies(1) * G : 0);
     return (size_t)kRows * rs * 4;

@@ -118,3 +118,17 @@ def test_default_plans_cover_every_length():
             assert 2 * p.G * p.Q - 1 >= M and 64 % p.G == 0
     with pytest.raises(hm.HmsvError):
         hm.default_plan("msv", 3840)
+
+
+def test_plan_lds_bytes():
+    """LDS footprint: 21 table rows of the lane groups' chunk regions; every
+    default plan fits one CU's 160 KiB; invalid shapes give 0."""
+    assert hm.plan_lds_bytes(8, 26) == 21 * 7 * 64 * 4       # 6 full chunks + a partial one
+    assert hm.plan_lds_bytes(64, 30) == 21 * 30 * 64 * 4     # one dword per lane and register
+    assert hm.plan_lds_bytes(32, 7) == 21 * (3 * 64 + 64) * 4  # 3 two-dword chunks + 1-dword tail
+    for G, Q in ((0, 4), (3, 4), (128, 1), (8, 0)):
+        assert hm.plan_lds_bytes(G, Q) == 0
+    for filt in ("msv", "ssv"):
+        for M in (1, 48, 63, 64, 127, 128, 400, 1000, 2400, 3839):
+            p = hm.default_plan(filt, M)
+            assert 0 < hm.plan_lds_bytes(p.G, p.Q) <= 160 * 1024
