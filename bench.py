@@ -10,7 +10,8 @@ that builds the profile's LDS image and the filter kernel), with the packed
 database already resident in HBM.  GCUPS = M x real residues / step time.
 
 The same line also reports:
-* ssv_m400: the SSV filter of an M=400 profile (seed 3) on the same database;
+* ssv: the SSV filter of profiles with M = 100, 400, 1000 and 2400 (seed 3)
+  on the same database, each checked in full against the oracle;
 * batched: 64 profiles with M ~ U{30..2400}, MSV/SSV alternating, against a
   1,000,000-sequence lognormal database (seed 4), one hipGraph launch vs 64
   sequential plain launches with the same plans (outputs must be identical;
@@ -180,19 +181,24 @@ def oracle_check(a, filt, emis, db, gs, gf, synth, ids=None):
 
 
 def ssv_leg(a, hm, torch, synth, h):
-    M = 400
-    emis = synth.sample_emissions(synth.streams(3)["profile"], M)
-    prof = hm.Profile.from_emissions(emis, synth.BG, h["gdb"].device)
-    plan = hm.plan_for("ssv", M)
-    wall, kern, score, flags = time_plain(hm, torch, "ssv", prof, h["gdb"], plan, 10, 2)
-    cells = M * h["db"].residues
-    bad, _ = oracle_check(a, "ssv", emis, h["db"], score.cpu().numpy(), flags.cpu().numpy(),
-                          synth)
-    return {"value": round(cells / wall / 1e9, 1), "unit": "GCUPS",
-            "kernel_ms": round(kern * 1e3, 4),
-            "frac": round(cells / kern * INSTR_PER_CELL["ssv"] / PEAK_INSTR, 4),
-            "plan": list(plan.as_tuple()),
-            "parity": "bit-exact" if bad == 0 else f"{bad} mismatches"}
+    """SSV on the same 500k database for the four profile lengths of the SSV
+    workload (seed 3): throughput, roofline fraction and full oracle parity."""
+    w = synth.plain_ssv(db=h["db"])
+    out = []
+    for emis in w.emissions:
+        M = emis.shape[0]
+        prof = hm.Profile.from_emissions(emis, synth.BG, h["gdb"].device)
+        plan = hm.plan_for("ssv", M)
+        wall, kern, score, flags = time_plain(hm, torch, "ssv", prof, h["gdb"], plan, 10, 2)
+        cells = M * h["db"].residues
+        bad, _ = oracle_check(a, "ssv", emis, h["db"], score.cpu().numpy(),
+                              flags.cpu().numpy(), synth)
+        out.append({"M": M, "value": round(cells / wall / 1e9, 1), "unit": "GCUPS",
+                    "kernel_ms": round(kern * 1e3, 4),
+                    "frac": round(cells / kern * INSTR_PER_CELL["ssv"] / PEAK_INSTR, 4),
+                    "plan": list(plan.as_tuple()),
+                    "parity": "bit-exact" if bad == 0 else f"{bad} mismatches"})
+    return {"workload": "ssv_500k_lognormal", "per_M": out}
 
 
 def batched_leg(a, hm, torch, synth):
@@ -314,7 +320,7 @@ def main():
                          f"{cpu_s:.1f} s wall"}
     extra = {}
     if not a.no_extra:
-        extra["ssv_m400"] = ssv_leg(a, hm, torch, synth, h)
+        extra["ssv"] = ssv_leg(a, hm, torch, synth, h)
     h["gdb"].close()
     if not a.no_extra:
         extra["batched"] = batched_leg(a, hm, torch, synth)

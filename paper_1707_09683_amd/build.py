@@ -27,7 +27,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # The atomic optimizer rewrites the work-queue atomic into a wave reduction
 # that reads its result back at once; the kernels defer that read to the
 # next sequence switch, so the rewrite is turned off.
-COMMON = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
+COMMON = ["-O3", f"--offload-arch={ARCH}", "-std=c++20", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
           "-I", CSRC, "-I", INCLUDE, "-Wno-unused-command-line-argument"]

@@ -40,6 +40,8 @@
 //    max(0, scB + max over its residues of max_k (dbias - cost_k)), computed
 //    at its end from a per-residue table.
 #pragma once
+#include <utility>
+#include <type_traits>
 #include "hmsv_internal.h"
 
 namespace hmsv {
@@ -212,6 +214,11 @@ struct Lane {
     __device__ __forceinline__ void row(const uint32_t *const (&T)[3], uint32_t x) {
         uint32_t c[Q];
         load_row(T[0], T[1], T[2], x, c);
+        update(c);
+    }
+
+    // The cell update of one row, given the row's scores.
+    __device__ __forceinline__ void update(const uint32_t (&c)[Q]) {
         uint32_t gam = shift_in(R[Q - 1]);
         uint32_t prev_v = 0;
 #pragma unroll
@@ -240,6 +247,10 @@ constexpr int kCtrMain = 0;      // next sequence of the range
 // record scores and hand out sequences (see filter_kernel).
 template <int G>
 constexpr int kExitGroups = G == 1 ? 8 : G == 2 ? 4 : G == 4 ? 2 : 1;
+
+// Lanes with at most this many registers read each row's scores one row
+// ahead (a second set of Q registers).
+constexpr int kPipeQ = 17;
 
 // Residue words (four residues each) per load and lane.
 template <int G>
@@ -454,18 +465,37 @@ filter_kernel(KArgs a) {
         const int e_min = n_act < kExitGroups<G> ? n_act : kExitGroups<G>;
         const uint32_t step = active ? 4u * K : 0u;
         bool ended = false;
+        // Short rows (Q <= kPipeQ) are latency bound when a wavefront runs
+        // alone (the last, longest sequences of a launch): their scores are
+        // read one row ahead, into two alternating register sets.
+        constexpr bool PIPE = Q <= kPipeQ;
+        uint32_t ca[PIPE ? Q : 1], cb[PIPE ? Q : 1];
+        auto xrow = [&](int r) -> uint32_t { return (wv[r / 4] >> (8 * (r % 4))) & 0xffu; };
+        if constexpr (PIPE) st.load_row(T[0], T[1], T[2], xrow(0), ca);
         do {
             uint32_t offn = off + step;
             if constexpr (kExitGroups<G> > 1) offn = offn < seq_end ? offn : seq_end;
             uint32_t wn[K];
             load_words(offn, wn);                                    // next 4K residues
-            if (!wave_exact) {
+            // one residue row; CHECK: MSV exact-mode check after it
+            auto one_row = [&](auto r_c, auto check_c) {
+                constexpr int r = decltype(r_c)::value;
+                if constexpr (PIPE) {
+                    uint32_t (&cur)[PIPE ? Q : 1] = (r & 1) ? cb : ca;
+                    uint32_t (&nxt)[PIPE ? Q : 1] = (r & 1) ? ca : cb;
+                    if constexpr (r + 1 < 4 * K) {
+                        st.load_row(T[0], T[1], T[2], xrow(r + 1), nxt);
+                    } else {
+                        // first row of the next step: its residues must be in
 #pragma unroll
-                for (int r = 0; r < 4 * K; ++r) st.row(T, (wv[r / 4] >> (8 * (r % 4))) & 0xffu);
-            } else if constexpr (MSV) {
-#pragma unroll
-                for (int r = 0; r < 4 * K; ++r) {
-                    st.row(T, (wv[r / 4] >> (8 * (r % 4))) & 0xffu);
+                        for (int k = 0; k < K; ++k) asm volatile("" : "+v"(wn[k]));
+                        st.load_row(T[0], T[1], T[2], wn[0] & 0xffu, nxt);
+                    }
+                    st.update(cur);
+                } else {
+                    st.row(T, xrow(r));
+                }
+                if constexpr (MSV && decltype(check_c)::value) {
                     // any cell above the level?  (saturating u16 subtract)
                     bool hit = (uint32_t)__builtin_bit_cast(
                         uint32_t, __builtin_elementwise_sub_sat(
@@ -493,9 +523,16 @@ filter_kernel(KArgs a) {
                         }
                     }
                 }
-            }
-            // Consume the next word only here, so its load stays issued before
-            // the four rows and its latency hides behind them.
+            };
+            auto all_rows = [&](auto check_c) {
+                [&]<int... R>(std::integer_sequence<int, R...>) {
+                    (one_row(std::integral_constant<int, R>{}, check_c), ...);
+                }(std::make_integer_sequence<int, 4 * K>{});
+            };
+            if (!wave_exact) all_rows(std::false_type{});
+            else all_rows(std::true_type{});
+            // Consume the next words only here, so their load stays issued
+            // before the rows and its latency hides behind them.
 #pragma unroll
             for (int k = 0; k < K; ++k) asm volatile("" : "+v"(wn[k]));
             off = offn;

@@ -115,6 +115,40 @@ def test_msv_exact_replay_of_j_state_sequences(hm, M):
 
 
 @pytest.mark.parametrize("filt", ["msv", "ssv"])
+@pytest.mark.parametrize("M", [48, 400])
+def test_long_sequences(hm, filt, M):
+    """Sequences of 1500..6000 residues, on both sides of the length above
+    which MSV runs exact from the start, with implants (hits, J loop,
+    overflow) placed anywhere along them."""
+    rng = np.random.default_rng(300 + M)
+    emis = synth.sample_emissions(rng, M)
+    db = _implanted_db(rng, emis, 300, 1500, 6000, 0.1)
+    _short_implants(rng, emis, db, 0.4)
+    print(f"case long {filt} M={M}", flush=True)
+    exp = _oracle(filt, emis, db)
+    _assert_same(_gpu(hm, filt, emis, db), exp, what=f"long {filt} M={M}")
+    if filt == "msv":
+        assert int(((exp[0] > 190) & (exp[1] == 0)).sum()) > 5
+        assert exp[1].sum() > 0
+
+
+def _short_implants(rng, emis, db, frac):
+    """Overwrite 1..3 segments of 5..12 residues emitted by consecutive
+    nodes of the profile into a fraction of the sequences: scores that open
+    the J loop without overflowing."""
+    M = emis.shape[0]
+    p = emis / emis.sum(axis=1, keepdims=True)
+    for i in np.flatnonzero(rng.random(db.n) < frac):
+        a, b = int(db.offsets[i]), int(db.offsets[i + 1])
+        for _ in range(int(rng.integers(1, 4))):
+            ln = int(min(rng.integers(5, 13), M, b - a))
+            k0 = int(rng.integers(0, M - ln + 1))
+            at = a + int(rng.integers(0, b - a - ln + 1))
+            for t in range(ln):
+                db.res[at + t] = rng.choice(20, p=p[k0 + t])
+
+
+@pytest.mark.parametrize("filt", ["msv", "ssv"])
 def test_edge_sequences(hm, filt):
     """Empty, all-invalid, single-residue, long (5000) sequences and
     single-sequence and sub-group-count databases."""
