@@ -24,7 +24,7 @@ TABLE = os.path.join(HERE, "tuned_plans.json")
 M_BINS = (30, 40, 48, 64, 80, 96, 128, 160, 192, 256, 320, 400, 512, 640, 768, 1024,
           1280, 1536, 2048, 2400, 3072, 3839)
 GROUPS = (1, 2, 4, 8, 16, 32, 64)
-WAVES = (2, 4, 8)
+WAVES = (2, 3, 4, 5, 6, 8)
 QMAX = 32
 LDS_LIMIT = 160 * 1024
 

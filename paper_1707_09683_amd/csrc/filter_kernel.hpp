@@ -252,12 +252,12 @@ constexpr int kExitGroups = G == 1 ? 8 : G == 2 ? 4 : G == 4 ? 2 : 1;
 // ahead (a second set of Q registers).
 constexpr int kPipeQ = 17;
 
-// Residue words (four residues each) per load and lane.
+// Residue words (four residues each) per load and lane: 16 or 8 residues.
 template <int G>
-constexpr int kWordsPerLoad = G <= 4 ? 4 : 1;
+constexpr int kWordsPerLoad = G <= 8 ? 4 : 2;
 
 // One filter launch.  Every lane group pulls sequences (longest first)
-// from the call's range and runs their rows in blocks of four residues.
+// from the call's range and runs their rows in steps of 4K residues.
 //
 // MSV first runs a sequence with scB fixed at sat0(base - tjb - tbm).
 // Cells only grow with scB, and scB keeps that value until the running max
@@ -310,11 +310,12 @@ filter_kernel(KArgs a) {
     bool ovf = false;
     bool active = false;
     bool need = false;           // group wants a sequence
-    // Residues come in words of four, K words per load: narrow groups (up
-    // to 32 sequences per wavefront, each streaming its own bytes) load 16
-    // residues per lane so each load is issued 16 rows before its first use;
-    // their sequences are then run in whole 16-row steps (the extra rows
-    // are non-scoring padding, which cannot change a score).
+    // Residues come in words of four, K words per load (16 residues for
+    // groups of up to 8 lanes, 8 for wider ones): each group streams its own
+    // sequence, and a load issued 4K rows before its first use hides the
+    // memory latency of the first touch of each line.  Sequences then run
+    // in whole 4K-row steps (the extra rows are non-scoring padding, which
+    // cannot change a score).
     constexpr int K = kWordsPerLoad<G>;
     uint32_t wv[K];              // next 4K residues of the group's sequence
 #pragma unroll
@@ -354,23 +355,25 @@ filter_kernel(KArgs a) {
     auto fetch = [&](int r, uint4 &h, uint4 &f) {
         const uint4 *p = recs + 2 * (r < nseq ? r : nseq - 1);
         h = p[0];
-        if constexpr (K == 4) f = p[1];
+        if constexpr (K > 1) f = p[1];
     };
     uint4 ra;                    // record A: off, rows | tjb << 24, id, first word
-    uint4 ra16;                  // record A's first sixteen residues (K = 4)
+    uint4 ra16;                  // record A's first sixteen residues (K > 1)
     int qa, qc;                  // records of A and of the claimed position (kNone: none)
     uint32_t pend_b = 0;
     int pend_first = -1;         // wave-uniform
     auto start_record = [&](const uint4 &r, const uint4 &r16, bool valid) {
         active = valid;
         uint32_t rows = r.y & kRowsMask;
-        if constexpr (K == 4) rows = (rows + 15u) & ~15u;
+        if constexpr (K > 1) rows = (rows + 4u * K - 1u) & ~(4u * K - 1u);
         seq_off = valid ? r.x : a.pad_off;
         seq_end = valid ? r.x + rows : a.pad_off;
         id = r.z;
         tjbm = (int)(r.y >> 24) + a.tbm;
         if constexpr (K == 4) {
             wv[0] = r16.x; wv[1] = r16.y; wv[2] = r16.z; wv[3] = r16.w;
+        } else if constexpr (K == 2) {
+            wv[0] = r16.x; wv[1] = r16.y;
         } else {
             wv[0] = r.w;
         }
@@ -380,6 +383,9 @@ filter_kernel(KArgs a) {
         if constexpr (K == 4) {
             uint4 v = *(const uint4 *)(a.res + o);
             d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        } else if constexpr (K == 2) {
+            uint2 v = *(const uint2 *)(a.res + o);
+            d[0] = v.x; d[1] = v.y;
         } else {
             d[0] = *(const uint32_t *)(a.res + o);
         }
