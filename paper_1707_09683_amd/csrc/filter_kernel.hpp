@@ -53,34 +53,23 @@ constexpr uint32_t kMinus2 = 0xC000u;        // fp16 -2.0: score of dummy/paddin
 constexpr int kBase = 190;
 constexpr int kTec = 3;
 
-// LDS reads.  gfx950's LDS serves 256 bytes (64 banks) per pass, so a
-// read instruction of w dwords per lane is served 64/w lanes at a time.
-// A lane's Q score pairs are read in chunks: full chunks of W dwords
-// (W = 64/G for groups of G >= 16 lanes, so one group fills a pass; W = 4,
-// the widest read, for narrower groups), then a 2-dword and/or a 1-dword
-// tail.  Groups that share a pass read different table rows; to keep them
-// on disjoint banks every chunk of width w is stored copies(w) = 64/(G w)
-// times side by side and group g reads copy g % copies(w).
-template <int G>
-constexpr int read_width() { return G >= 16 ? 64 / G : 4; }
-
+// The lane's view of the profile's LDS image (lds_layout in
+// hmsv_internal.h describes the image).
 template <int G, int Q>
 struct Layout {
-    static constexpr int W = read_width<G>();
-    // With 4-dword chunks a partial last chunk is read whole (its unused
-    // dwords are padding): one LDS address per row serves every read.
-    static constexpr bool WIDE_TAIL = W == 4 && Q % 4 != 0;
-    static constexpr int NF = WIDE_TAIL ? Q / W + 1 : Q / W;   // chunks of W dwords
-    static constexpr int R = WIDE_TAIL ? 0 : Q - NF * W;      // tail dwords (0..W-1)
+    static constexpr LdsLayout D = lds_layout(G, Q);
+    static constexpr int W = 4;                       // dwords per chunk read
+    static constexpr int NF = D.NF;
+    static constexpr int R = D.R;
     static constexpr bool T2 = (R & 2) != 0;
     static constexpr bool T1 = (R & 1) != 0;
-    static constexpr int copies(int w) { return 64 / (G * w) > 1 ? 64 / (G * w) : 1; }
-    static constexpr int CW = copies(W) * G * W;      // dwords of one full chunk, all copies
-    static constexpr int OFF2 = NF * CW;
-    static constexpr int OFF1 = OFF2 + (T2 ? copies(2) * G * 2 : 0);
-    static constexpr int RS = OFF1 + (T1 ? copies(1) * G : 0);   // dwords per table row
+    static constexpr int CW = D.CW;
+    static constexpr int OFF2 = D.OFF2;
+    static constexpr int OFF1 = D.OFF1;
+    static constexpr int RS = D.RS;
     static constexpr int Q2 = NF * W;                 // first register of the 2-dword tail
     static constexpr int Q1 = NF * W + (T2 ? 2 : 0);  // register of the 1-dword tail
+    static constexpr int copies(int w) { return lds_copies(G, w); }
     __device__ static int lane_off(int lane, int w) {
         return ((lane / G) % copies(w)) * G * w + (lane % G) * w;
     }
@@ -189,18 +178,11 @@ struct Lane {
 #pragma unroll
         for (int ch = 0; ch < Lay::NF; ++ch) {
             const uint32_t *p = at(TW) + ch * Lay::CW;
-            if constexpr (W == 4) {
-                uint4 v = *(const uint4 *)p;
-                if (ch * 4 + 0 < Q) c[ch * 4 + 0] = v.x;
-                if (ch * 4 + 1 < Q) c[ch * 4 + 1] = v.y;
-                if (ch * 4 + 2 < Q) c[ch * 4 + 2] = v.z;
-                if (ch * 4 + 3 < Q) c[ch * 4 + 3] = v.w;
-            } else if constexpr (W == 2) {
-                uint2 v = *(const uint2 *)p;
-                c[ch * 2 + 0] = v.x; c[ch * 2 + 1] = v.y;
-            } else {
-                c[ch] = p[0];
-            }
+            uint4 v = *(const uint4 *)p;
+            if (ch * 4 + 0 < Q) c[ch * 4 + 0] = v.x;
+            if (ch * 4 + 1 < Q) c[ch * 4 + 1] = v.y;
+            if (ch * 4 + 2 < Q) c[ch * 4 + 2] = v.z;
+            if (ch * 4 + 3 < Q) c[ch * 4 + 3] = v.w;
         }
         if constexpr (Lay::T2) {
             uint2 v = *(const uint2 *)at(T2);

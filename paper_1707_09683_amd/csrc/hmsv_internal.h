@@ -61,17 +61,44 @@ struct KernelEntry {
     OccupancyFn occupancy;
 };
 
-// Size of a plan's LDS image: mirrors Layout in filter_kernel.hpp (full
-// chunks of W dwords and 2-/1-dword tails, each stored 64/(G w) times).
-inline size_t lds_bytes(int G, int Q) {
-    int W = G >= 16 ? 64 / G : 4;
-    auto copies = [G](int w) { return 64 / (G * w) > 1 ? 64 / (G * w) : 1; };
-    int nf = Q / W, r = Q - nf * W;
-    if (W == 4 && r != 0) { nf += 1; r = 0; }    // partial last chunk read whole
-    size_t rs = (size_t)nf * copies(W) * G * W + ((r & 2) ? (size_t)copies(2) * G * 2 : 0) +
-                ((r & 1) ? (size_t)copies(1) * G : 0);
-    return (size_t)kRows * rs * 4;
+// The profile's LDS image: kRows table rows of RS dwords.  A lane reads its
+// Q score pairs in chunks of 4 dwords (ds_read_b128), then a 2-dword and/or
+// a 1-dword tail; a partial last chunk is instead read whole (its unused
+// dwords are padding) when the padded table still fits, so one LDS address
+// per row serves every read.  gfx950's LDS serves 256 bytes (64 banks) per
+// pass, so a read of w dwords per lane is served 64/w lanes at a time: the
+// groups of G lanes that share a pass read different table rows, and to
+// keep them on disjoint banks a chunk of width w is stored
+// copies(w) = max(1, 64/(G w)) times side by side, group g reading copy
+// g % copies(w).  A group of 16 or more lanes fills a pass by itself.
+// Dwords of the row: NF chunk regions of CW, then the tails at OFF2, OFF1.
+struct LdsLayout {
+    int NF;      // 4-dword chunks (the last one partial if WIDE)
+    int R;       // tail dwords after them (0..3)
+    bool WIDE;   // partial last chunk read whole
+    int CW;      // dwords of one chunk region (all copies)
+    int OFF2;    // the 2-dword tail region
+    int OFF1;    // the 1-dword tail region
+    int RS;      // dwords per table row
+};
+
+constexpr int lds_copies(int G, int w) { return 64 / (G * w) > 1 ? 64 / (G * w) : 1; }
+
+constexpr LdsLayout lds_layout(int G, int Q) {
+    LdsLayout L{};
+    L.CW = lds_copies(G, 4) * G * 4;
+    int nf = Q / 4, r = Q % 4;
+    L.WIDE = r != 0 && (size_t)kRows * (size_t)(nf + 1) * (size_t)L.CW * 4 <= kLdsBytes;
+    L.NF = L.WIDE ? nf + 1 : nf;
+    L.R = L.WIDE ? 0 : r;
+    L.OFF2 = L.NF * L.CW;
+    L.OFF1 = L.OFF2 + ((L.R & 2) ? lds_copies(G, 2) * G * 2 : 0);
+    L.RS = L.OFF1 + ((L.R & 1) ? lds_copies(G, 1) * G : 0);
+    return L;
 }
+
+inline size_t lds_bytes(int G, int Q) { return (size_t)kRows * lds_layout(G, Q).RS * 4; }
+
 // A group of G lanes with Q registers covers nodes 1..2GQ-1 (slot 0 is a
 // dummy -inf node).
 inline int64_t plan_nodes(int G, int Q) { return (int64_t)2 * G * Q - 1; }
