@@ -269,12 +269,14 @@ def served_leg(a, hm, torch, synth):
     plain = sv.Server(gdb, synth.BG, max_inflight=1, depth=1, chunk_cells=float("inf"))
     reqs, span = sv.replay(plain, np.zeros(len(cal[0])), cal[2], cal[3])
     service = span / len(reqs)
+    rate = float(np.sum(cal[1])) * db.residues / span          # cells/s, back to back
     qps = 0.7 / service
     arr, Ms, filt, emis = synth.request_trace(5, a.serve_requests, qps)
     cells = int(np.sum(Ms)) * db.residues
     reqs_p, span_p = sv.replay(plain, arr, filt, emis)
     plain.close()
-    srv = sv.Server(gdb, synth.BG, max_inflight=8, depth=3, chunk_cells=1e11, aging=1.0)
+    srv = sv.Server(gdb, synth.BG, max_inflight=8, depth=2, chunk_cells=2e11, aging=1.0,
+                    rate=rate)
     reqs_s, span_s = sv.replay(srv, arr, filt, emis)
     srv.close()
     same = all(np.array_equal(x.future.result()[0], y.future.result()[0]) and
@@ -298,8 +300,8 @@ def main():
         calibrate_copy(a.calibrate_copy)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the filter shards "
-                          "by database sequences with no exchange (see DESIGN.md)"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1 (the filters shard by "
+                          "database sequences with no exchange between GPUs)"}))
         sys.exit(2)
     import torch
     import synth

@@ -109,9 +109,9 @@ class _Slot:
 
 
 class Server:
-    def __init__(self, db: Database, bg, device="cuda", max_inflight=8, depth=3,
-                 chunk_cells=1e11, hbm_budget=2 << 30, lds_budget=160 * 1024,
-                 poll_s=100e-6, aging=1.0, rate=2.0e13):
+    def __init__(self, db: Database, bg, device="cuda", max_inflight=8, depth=2,
+                 chunk_cells=2e11, hbm_budget=2 << 30, lds_budget=160 * 1024,
+                 poll_s=100e-6, aging=1.0, rate=3.0e13):
         self.db = db
         self.bg = np.asarray(bg, dtype=np.float64)
         self.device = torch.device(device)
@@ -125,6 +125,7 @@ class Server:
         # is FIFO, large aging is shortest-remaining-work first; in between,
         # short requests overtake long ones only while the long ones have not
         # waited longer than their own remaining run time (scaled by aging).
+        # rate (cells/s) should be the device's measured throughput.
         self.aging = aging
         self.rate = rate
         order = db.order()
