@@ -105,13 +105,15 @@ int64_t hmsv_db_residues(const hmsv_db *db);     /* real residues (no padding) *
 int64_t hmsv_db_padded_rows(const hmsv_db *db);  /* rows the kernels run */
 
 /* ---- launch plan --------------------------------------------------------
- * How one filter call maps onto the GPU.  A lane group of G lanes (1..64)
- * aligns one sequence; each lane holds Q packed pairs of cells, so the
- * group covers 2*G*Q - 1 >= M nodes (one cell is a fixed -inf node).  64/G sequences share a wavefront (the
- * paper's multi-sequence alignment, Sec. 3.1 tier 4).  waves_per_block
- * wavefronts share one LDS copy of the profile; blocks = 0 picks a
- * persistent grid of the resident maximum.  tile is kept for plan-table
- * compatibility (a multiple of 4) and no longer affects the kernels. */
+ * How one filter call maps onto the GPU.  A lane group of G lanes (a power
+ * of two, 1..64) aligns one sequence; each lane holds Q packed pairs of
+ * cells, so the group covers 2*G*Q - 1 >= M nodes (one cell is a fixed
+ * -inf node).  64/G sequences share a wavefront (the paper's
+ * multi-sequence alignment, Sec. 3.1 tier 4).  waves_per_block (1..8, or
+ * 1..16 for G >= 32) wavefronts share one LDS copy of the profile;
+ * blocks = 0 picks a persistent grid of the resident maximum.  tile is
+ * kept for plan-table compatibility (a multiple of 4) and no longer
+ * affects the kernels. */
 typedef struct {
     int32_t G;
     int32_t Q;

@@ -44,7 +44,7 @@ def candidates(filt, M):
         Q = q_for(G, M)
         if Q > QMAX or lds_bytes(G, Q) > LDS_LIMIT:
             continue
-        for wpb in WAVES:
+        for wpb in WAVES + ((12, 16) if G >= 32 else ()):
             yield (G, Q, wpb, 0, 64)
 
 

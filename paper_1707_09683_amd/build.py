@@ -100,6 +100,66 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
     return LIB
 
 
+def resources(jobs: int | None = None) -> str:
+    """Compiler resource usage of the tuned plans' filter kernels, as a
+    markdown table: VGPRs, SGPRs, scratch and the occupancy the compiler
+    reports, the LDS image, and the wavefronts per SIMD the launch gets
+    (VGPRs, LDS and waves per block together).  Compiles the kernel units
+    again with -Rpass-analysis=kernel-resource-usage (no library is built)."""
+    import json
+    import re
+    import tempfile
+    table = json.load(open(os.path.join(HERE, "tuned_plans.json")))
+    key = next(k for k in table if not k.startswith("_"))
+    want = {}
+    for filt in ("msv", "ssv"):
+        for M, (G, Q, wpb, _b, _t) in table[key][filt].items():
+            want.setdefault((filt, G, Q), []).append((int(M), wpb))
+    units = sorted({(G, lo, hi) for _f, G, Q in want for (GG, lo, hi) in kernel_units()
+                    if GG == G and lo <= Q <= hi})
+    rx = re.compile(r"remark:\s+(Function Name|VGPRs|TotalSGPRs|ScratchSize \[bytes/lane\]|"
+                    r"Occupancy \[waves/SIMD\]): (\S+)")
+    usage = {}
+
+    def one(unit):
+        G, lo, hi = unit
+        with tempfile.TemporaryDirectory() as td:
+            cmd = [HIPCC, *COMMON, f"-DHMSV_G={G}", f"-DHMSV_QLO={lo}", f"-DHMSV_QHI={hi}",
+                   "--cuda-device-only", "-c", os.path.join(CSRC, "kernels.hip"),
+                   "-o", os.path.join(td, "k.o"), "-Rpass-analysis=kernel-resource-usage"]
+            return subprocess.run(cmd, capture_output=True, text=True).stderr
+
+    with cf.ThreadPoolExecutor(max_workers=jobs or 8) as ex:
+        for err in ex.map(one, units):
+            cur = None
+            for m in rx.finditer(err):
+                k, v = m.group(1), m.group(2)
+                if k == "Function Name":
+                    mm = re.search(r"filter_kernelILi(\d+)ELi(\d+)ELi(\d)ELi(\d+)E", v)
+                    cur = (("msv" if mm.group(3) == "1" else "ssv"), int(mm.group(1)),
+                           int(mm.group(2)), int(mm.group(4))) if mm else None
+                    if cur:
+                        usage[cur] = {}
+                elif cur:
+                    usage[cur][k] = int(v)
+    sys.path.insert(0, ROOT)
+    from paper_1707_09683_amd import plan_lds_bytes
+    lines = ["| filter | M-bins | G | Q | waves/block | VGPRs | SGPRs | scratch B/lane | "
+             "waves/SIMD (VGPRs) | LDS KiB/block | waves/SIMD (launch) |",
+             "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for (filt, G, Q), uses in sorted(want.items(), key=lambda t: (t[0][0], min(t[1])[0])):
+        lds = plan_lds_bytes(G, Q)
+        for wpb in sorted({w for _m, w in uses}):
+            u = usage.get((filt, G, Q, 1024 if wpb > 8 else 512), {})
+            bins = ",".join(str(m) for m, w in sorted(uses) if w == wpb)
+            occ_v = u.get("Occupancy [waves/SIMD]", 0)
+            blocks = min(160 * 1024 // lds, (4 * occ_v) // wpb) if lds else 0
+            lines.append(f"| {filt} | {bins} | {G} | {Q} | {wpb} | {u.get('VGPRs')} | "
+                         f"{u.get('TotalSGPRs')} | {u.get('ScratchSize [bytes/lane]')} | "
+                         f"{occ_v} | {lds / 1024:.1f} | {blocks * wpb / 4:g} |")
+    return "\n".join(lines)
+
+
 def clean():
     shutil.rmtree(OBJ, ignore_errors=True)
     if os.path.exists(LIB):
@@ -111,6 +171,11 @@ if __name__ == "__main__":
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--incremental", action="store_true")
     ap.add_argument("-v", "--verbose", action="store_true")
+    ap.add_argument("--resources", action="store_true",
+                    help="print the tuned plans' compiler resource usage instead of building")
     a = ap.parse_args()
+    if a.resources:
+        print(resources(a.jobs))
+        sys.exit(0)
     print(build(a.jobs, a.incremental, a.verbose))
     sys.exit(0)

@@ -250,8 +250,8 @@ constexpr int kWordsPerLoad = G <= 8 ? 4 : 2;
 // cell passed the level at which scB would change or overflow occurs, and
 // only then runs Alg. 2's special-state update (group max, new scB, cells
 // lowered by the rise).  Waves without a group in exact mode skip the check.
-template <int G, int Q, int MODE>
-__global__ void __launch_bounds__(512)
+template <int G, int Q, int MODE, int THREADS>
+__global__ void __launch_bounds__(THREADS)
 filter_kernel(KArgs a) {
     constexpr bool MSV = MODE == kMSV;
     extern __shared__ uint32_t lds[];
@@ -634,38 +634,64 @@ __global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks) {
                            : slot_bits<MSV>(a, x, s0) | (slot_bits<MSV>(a, x, s0 + Q) << 16);
 }
 
+// Block sizes: up to 8 wavefronts, or up to 16 for groups of 32 and 64 lanes
+// (their large LDS tables allow one block per CU, so a 16-wavefront block is
+// the only way to four wavefronts per SIMD).  Each size is its own kernel:
+// the compiler budgets registers for the block size it is told.
+template <int G>
+constexpr int kMaxWaves = G >= 32 ? 16 : 8;
+
+template <int G, int Q, int MODE, int THREADS>
+hipError_t launch_filter_kernel(const KArgs &a, int wpb, int blocks, hipStream_t s) {
+    size_t lds = lds_bytes(G, Q);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)filter_kernel<G, Q, MODE, THREADS>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((filter_kernel<G, Q, MODE, THREADS>), dim3(blocks), dim3(wpb * 64), lds,
+                       s, a);
+    return hipGetLastError();
+}
+
 // prep (LDS image, counter, MSV best scores), then the filter kernel.
 template <int G, int Q, bool MSV>
 hipError_t launch_filter(const KArgs &a, int wpb, int blocks, hipStream_t s) {
     constexpr int MODE = MSV ? kMSV : kSSV;
     constexpr int n = kRows * Layout<G, Q>::RS;
     constexpr int nb = (n + 255) / 256;
+    if (wpb < 1 || wpb > kMaxWaves<G>) return hipErrorInvalidValue;
     hipLaunchKernelGGL((prep_kernel<G, Q, MSV>), dim3(nb + (MSV ? kRows : 0)), dim3(256), 0, s,
                        a, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t lds = lds_bytes(G, Q);
-    if (lds > 64 * 1024) {
-        e = hipFuncSetAttribute((const void *)filter_kernel<G, Q, MODE>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
+    if constexpr (kMaxWaves<G> > 8) {
+        if (wpb > 8) return launch_filter_kernel<G, Q, MODE, 1024>(a, wpb, blocks, s);
     }
-    hipLaunchKernelGGL((filter_kernel<G, Q, MODE>), dim3(blocks), dim3(wpb * 64), lds, s, a);
-    return hipGetLastError();
+    return launch_filter_kernel<G, Q, MODE, 512>(a, wpb, blocks, s);
+}
+
+template <int G, int Q, int MODE, int THREADS>
+int occupancy_kernel(int wpb) {
+    int nb = 0;
+    size_t lds = lds_bytes(G, Q);
+    if (hipFuncSetAttribute((const void *)filter_kernel<G, Q, MODE, THREADS>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, filter_kernel<G, Q, MODE, THREADS>,
+                                                     wpb * 64, lds) != hipSuccess)
+        return 0;
+    return nb;
 }
 
 template <int G, int Q, bool MSV>
 int occupancy_filter(int wpb) {
     constexpr int MODE = MSV ? kMSV : kSSV;
-    int nb = 0;
-    size_t lds = lds_bytes(G, Q);
-    if (hipFuncSetAttribute((const void *)filter_kernel<G, Q, MODE>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, filter_kernel<G, Q, MODE>, wpb * 64, lds)
-        != hipSuccess)
-        return 0;
-    return nb;
+    if (wpb < 1 || wpb > kMaxWaves<G>) return 0;
+    if constexpr (kMaxWaves<G> > 8) {
+        if (wpb > 8) return occupancy_kernel<G, Q, MODE, 1024>(wpb);
+    }
+    return occupancy_kernel<G, Q, MODE, 512>(wpb);
 }
 
 }  // namespace hmsv

@@ -98,7 +98,8 @@ hmsv_status check_plan(const hmsv_plan *pl, int M) {
     if (pl->G < 1 || pl->G > 64 || (64 % pl->G) != 0) return HMSV_EINVAL;
     if (pl->Q < 1) return HMSV_EINVAL;
     if (plan_nodes(pl->G, pl->Q) < M) return HMSV_EINVAL;
-    if (pl->waves_per_block < 1 || pl->waves_per_block > 8) return HMSV_EINVAL;
+    if (pl->waves_per_block < 1 || pl->waves_per_block > (pl->G >= 32 ? 16 : 8))
+        return HMSV_EINVAL;
     if (pl->blocks < 0) return HMSV_EINVAL;
     if (pl->tile < 4 || (pl->tile % 4) != 0) return HMSV_EINVAL;
     if (lds_bytes(pl->G, pl->Q) > (size_t)kLdsBytes) return HMSV_EUNSUPPORTED;
