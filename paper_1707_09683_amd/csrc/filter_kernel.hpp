@@ -233,6 +233,7 @@ constexpr int kExitGroups = G == 1 ? 8 : G == 2 ? 4 : G == 4 ? 2 : 1;
 // Lanes with at most this many registers read each row's scores one row
 // ahead (a second set of Q registers).
 constexpr int kPipeQ = 17;
+constexpr int kPipeQMSV = 13;     // MSV also holds its exact-mode state
 
 // Residue words (four residues each) per load and lane: 16 or 8 residues.
 template <int G>
@@ -456,7 +457,7 @@ filter_kernel(KArgs a) {
         // Short rows (Q <= kPipeQ) are latency bound when a wavefront runs
         // alone (the last, longest sequences of a launch): their scores are
         // read one row ahead, into two alternating register sets.
-        constexpr bool PIPE = Q <= kPipeQ;
+        constexpr bool PIPE = Q <= (MSV ? kPipeQMSV : kPipeQ);
         uint32_t ca[PIPE ? Q : 1], cb[PIPE ? Q : 1];
         auto xrow = [&](int r) -> uint32_t { return (wv[r / 4] >> (8 * (r % 4))) & 0xffu; };
         if constexpr (PIPE) st.load_row(T[0], T[1], T[2], xrow(0), ca);
