@@ -104,8 +104,18 @@ __device__ __forceinline__ int lane_max_bits(uint32_t v) {
 
 template <int G>
 __device__ __forceinline__ int group_max(int m) {
+    // within 16 lanes by DPP (quad swaps, then the half-row and row mirrors),
+    // beyond by lane shuffles; every lane of the group ends with the maximum
+    auto dmax = [](int v, auto ctrl) {
+        int t = __builtin_amdgcn_update_dpp(0, v, decltype(ctrl)::value, 0xf, 0xf, true);
+        return v > t ? v : t;
+    };
+    if constexpr (G >= 2) m = dmax(m, std::integral_constant<int, 0xB1>{});   // lane ^ 1
+    if constexpr (G >= 4) m = dmax(m, std::integral_constant<int, 0x4E>{});   // lane ^ 2
+    if constexpr (G >= 8) m = dmax(m, std::integral_constant<int, 0x141>{});  // 7 - lane in 8
+    if constexpr (G >= 16) m = dmax(m, std::integral_constant<int, 0x140>{}); // 15 - lane in 16
 #pragma unroll
-    for (int o = 1; o < G; o <<= 1) {
+    for (int o = 16; o < G; o <<= 1) {
         int t = __shfl_xor(m, o);
         m = m > t ? m : t;
     }
