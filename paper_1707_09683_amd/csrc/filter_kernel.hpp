@@ -430,7 +430,7 @@ filter_kernel(KArgs a) {
             // resolve the previous claim (its atomic has long returned); a
             // group with a pending claim holds -1 - its rank in qc
             if (pend_first >= 0) {
-                int b = __shfl((int)pend_b, pend_first);
+                int b = __builtin_amdgcn_readlane((int)pend_b, pend_first);
                 if (qc < 0) qc = record_of(3 * ngroups + b - 1 - qc);
             }
             if (need) {
@@ -445,8 +445,8 @@ filter_kernel(KArgs a) {
             int first = __ffsll((long long)m) - 1;
             if (lane == first) pend_b = atomicAdd(a.counter + kCtrMain, (uint32_t)__popcll(m));
             pend_first = first;
-            int rank = __popcll(m & ((1ull << lane) - 1ull));
-            rank = __shfl(rank, lane - j);
+            // the group's rank: claiming groups below its first lane
+            int rank = __popcll(m & ((1ull << (lane - j)) - 1ull));
             if (need) qc = -1 - rank;
             need = false;
         }
