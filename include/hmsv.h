@@ -134,7 +134,9 @@ size_t hmsv_plan_lds_bytes(int32_t G, int32_t Q);
 
 /* Device workspace needed by a scoring call on a database of nseq
  * sequences (bytes): the work-queue counters, the MSV per-residue best
- * scores and the profile converted to the kernel's LDS layout. */
+ * scores, the profile converted to the kernel's LDS layout, and the
+ * records of split sequences' segments (at most 32768 segments of 16384
+ * sequences per call; 1.4 MB in all). */
 size_t hmsv_workspace_bytes(int64_t nseq);
 
 /* ---- scoring -----------------------------------------------------------
@@ -148,7 +150,17 @@ size_t hmsv_workspace_bytes(int64_t nseq);
  * workspace must be ordered on one stream.  plan: NULL for the default.  The call allocates nothing.
  * Fails with HMSV_EINVAL on null pointers or a profile outside its
  * preconditions, HMSV_ENOKERNEL if the plan was not instantiated,
- * HMSV_EDEVICE if the launch fails. */
+ * HMSV_EDEVICE if the launch fails.
+ *
+ * A launch takes at least as long as one lane group needs for its longest
+ * sequence.  Sequences much longer than the launch's mean work per lane
+ * group (total rows / lane groups) are therefore cut into segments of about
+ * that many rows, scored in parallel and combined: each segment starts
+ * M - 1 rows (rounded up to 16) before its own rows, so all of its own
+ * cells are exact (a cell depends only on the M rows above it along its
+ * diagonal), and the sequence's maximum is the maximum over its segments.
+ * An MSV sequence whose combined maximum shows the J state may have opened
+ * is rescored whole, in order.  Scores are the same either way. */
 hmsv_status hmsv_msv_score(const hmsv_profile *prof, const hmsv_db *db,
                            uint8_t *score, uint8_t *flags, void *workspace,
                            const hmsv_plan *plan, hipStream_t stream);
@@ -170,6 +182,16 @@ hmsv_status hmsv_msv_score_range(const hmsv_profile *prof, const hmsv_db *db, in
 hmsv_status hmsv_ssv_score_range(const hmsv_profile *prof, const hmsv_db *db, int64_t first,
                                  int64_t count, int8_t *score, uint8_t *flags,
                                  void *workspace, const hmsv_plan *plan, hipStream_t stream);
+
+/* How a scoring call with this filter, profile length, plan (NULL: the
+ * default) and range (first = 0, count = -1: the whole database) splits its
+ * longest sequences: *nsplit sequences into *nsegs segments of *seg_rows
+ * rows each (the last segment of a sequence may be shorter).  For
+ * diagnostics and tests; persistent-grid plans need the device the call
+ * would run on.  Fails as the scoring calls do on a bad plan or range. */
+hmsv_status hmsv_split_info(const hmsv_db *db, int64_t first, int64_t count, int32_t is_msv,
+                            int32_t M, const hmsv_plan *plan, int32_t *nsplit,
+                            int32_t *nsegs, int32_t *seg_rows);
 
 /* Processing order of a packed database: ids[t] = original index of the
  * t-th sequence (longest first; ties keep the original order).

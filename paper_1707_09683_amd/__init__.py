@@ -94,13 +94,17 @@ for _f in ("hmsv_msv_score_range", "hmsv_ssv_score_range"):
                                   ctypes.POINTER(Plan), _P]
 _lib.hmsv_db_order.restype = ctypes.c_int
 _lib.hmsv_db_order.argtypes = [_P, _P]
+_lib.hmsv_split_info.restype = ctypes.c_int
+_lib.hmsv_split_info.argtypes = [_P, _i64, _i64, _i32, _i32, ctypes.POINTER(Plan),
+                                 ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
 
 EXPORTED = ("hmsv_strerror", "hmsv_tbm", "hmsv_tjb", "hmsv_quantize", "hmsv_db_create",
             "hmsv_db_destroy", "hmsv_db_nseq", "hmsv_db_residues", "hmsv_db_padded_rows",
             "hmsv_default_plan", "hmsv_plan_lds_bytes", "hmsv_workspace_bytes",
             "hmsv_msv_score", "hmsv_ssv_score",
             "hmsv_batch_create", "hmsv_batch_launch", "hmsv_batch_destroy",
-            "hmsv_msv_score_range", "hmsv_ssv_score_range", "hmsv_db_order")
+            "hmsv_msv_score_range", "hmsv_ssv_score_range", "hmsv_db_order",
+            "hmsv_split_info")
 
 
 def _check(rc: int, what: str):
@@ -285,6 +289,18 @@ def msv_score(profile, db, score=None, flags=None, workspace=None, plan=None, st
 def ssv_score(profile, db, score=None, flags=None, workspace=None, plan=None, stream=None):
     """SSV filter (paper Alg. 7): int8 scores and overflow flags per sequence."""
     return _score("ssv", profile, db, score, flags, workspace, plan, stream)
+
+
+def split_info(filt, M, db, plan=None, first=0, count=-1):
+    """(split sequences, segments, rows per segment) of a scoring call with
+    this filter, profile length and plan on positions [first, first+count)
+    of the processing order (count -1: the whole database)."""
+    ns, nseg, T = _i32(), _i32(), _i32()
+    pl = ctypes.byref(plan) if plan is not None else None
+    _check(_lib.hmsv_split_info(db._h, int(first), int(count), 1 if filt == "msv" else 0,
+                                int(M), pl, ctypes.byref(ns), ctypes.byref(nseg),
+                                ctypes.byref(T)), "hmsv_split_info")
+    return ns.value, nseg.value, T.value
 
 
 def score_range(filt, profile, db, first, count, score, flags, workspace=None, plan=None,

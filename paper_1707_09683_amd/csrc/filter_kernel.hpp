@@ -333,20 +333,27 @@ filter_kernel(KArgs a) {
     // dynamically) the records in between, longest first.  No group thus
     // queues a long sequence behind its first one.  Ranges with fewer than
     // 3N records use positions as record numbers.
+    //
+    // The records are the range's with its split sequences (records
+    // [0, nsplit)) replaced by their segments: nv = nsegs + nseq - nsplit
+    // records, the segments first.
     const uint4 *recs = (const uint4 *)a.seqs;
-    const int nseq = a.nseq;                      // ranges are never empty
+    const uint4 *segs = (const uint4 *)a.segs;
+    const int nsegs = a.nsegs;
+    const int nv = nsegs + a.nseq - a.nsplit;     // ranges are never empty
     const int ngroups = (int)(gridDim.x * (blockDim.x / G));
     const int gid = (int)(blockIdx.x * (blockDim.x / G) + threadIdx.x / G);
-    const bool tail = nseq >= 3 * ngroups;
+    const bool tail = nv >= 3 * ngroups;
     constexpr int kNone = 0x7fffffff;             // position past the range
     auto record_of = [&](int p) -> int {          // queue position -> record
-        if (p >= nseq) return kNone;
+        if (p >= nv) return kNone;
         if (!tail || p < ngroups) return p;
-        if (p < 3 * ngroups) return nseq - 1 - (p - ngroups);
+        if (p < 3 * ngroups) return nv - 1 - (p - ngroups);
         return p - 2 * ngroups;
     };
     auto fetch = [&](int r, uint4 &h, uint4 &f) {
-        const uint4 *p = recs + 2 * (r < nseq ? r : nseq - 1);
+        r = r < nv ? r : nv - 1;
+        const uint4 *p = r < nsegs ? segs + 2 * r : recs + 2 * (r - nsegs + a.nsplit);
         h = p[0];
         if constexpr (K > 1) f = p[1];
     };
@@ -454,9 +461,9 @@ filter_kernel(KArgs a) {
         const bool wave_exact = MSV && __any(exact);
 
         // ---- rows, four residues at a time --------------------------------
-        // A group that reaches its end stays there: its offset stops at the
-        // end, where a word of non-scoring residues follows every sequence,
-        // so its cells fall to zero and its running max is kept.  The rows
+        // A group that reaches its end parks: its offset moves to the
+        // non-scoring residues after the database, so its cells fall to zero
+        // and its running max is kept.  The rows
         // continue until kExitGroups<G> groups of the wavefront have ended
         // (all of them if fewer are active), so narrow groups pay for the
         // switch code once per several sequence ends.
@@ -473,7 +480,7 @@ filter_kernel(KArgs a) {
         if constexpr (PIPE) st.load_row(T[0], T[1], T[2], xrow(0), ca);
         do {
             uint32_t offn = off + step;
-            if constexpr (kExitGroups<G> > 1) offn = offn < seq_end ? offn : seq_end;
+            if constexpr (kExitGroups<G> > 1) offn = offn < seq_end ? offn : a.pad_off;
             uint32_t wn[K];
             load_words(offn, wn);                                    // next 4K residues
             // one residue row; CHECK: MSV exact-mode check after it
@@ -535,7 +542,7 @@ filter_kernel(KArgs a) {
 #pragma unroll
             for (int k = 0; k < K; ++k) asm volatile("" : "+v"(wn[k]));
             off = offn;
-            ended = active && off == seq_end;
+            ended = active && off == (kExitGroups<G> > 1 ? a.pad_off : seq_end);
 #pragma unroll
             for (int k = 0; k < K; ++k) wv[k] = wn[k];
         } while (__popcll(__ballot(ended && gstart)) < e_min);
@@ -561,43 +568,141 @@ filter_kernel(KArgs a) {
         } else {
             mx = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
         }
-        bool redo = false;
-        if constexpr (MSV) {
+        // A segment's maximum goes into its sequence's slot; the group that
+        // ends the last segment finishes the sequence with the maximum over
+        // all of them (every cell of the sequence lies in some segment's own
+        // rows, and a warm-up row's cells never exceed the true ones).  In
+        // the group's first lane: true if the sequence is finished, with m,
+        // s and rec replaced by its maximum, original index and record.
+        // MSV also keeps the offset of the first segment whose maximum
+        // passed base + tec (hot): scB cannot move before that segment's
+        // own rows, so a rescoring in exact mode can start at its first
+        // warm-up row with fresh cells (those rows' cells stay below the
+        // true ones, hence below base + tec).
+        auto combine = [&](int &m, uint32_t &s, int &rec, uint32_t &hot) -> bool {
+            uint32_t *sl = a.slots + kSlotWords * (s & ~kSegBit);
+            atomicMax(sl + 1, (uint32_t)m);
+            if (MSV && m > kBase + kTec) atomicMin(sl + 4, seq_off);
+            __threadfence();
+            if (atomicSub(sl, 1u) != 1u) return false;
+            __threadfence();
+            m = (int)atomicMax(sl + 1, 0u);
+            if (MSV) hot = atomicMin(sl + 4, 0xffffffffu);
+            s = sl[2];
+            rec = (int)sl[3];
+            return true;
+        };
+        if constexpr (MODE == kSSV) {
+            if (ended && gstart) {
+                int m = mx, rec = 0;
+                uint32_t s = id, hot = 0;
+                if (!(id & kSegBit) || combine(m, s, rec, hot)) {
+                    bool of = m >= 255;
+                    a.score[s] = of ? (uint8_t)127 : (uint8_t)(int8_t)(m - 128);
+                    a.flag[s] = of ? 1 : 0;
+                }
+            }
+            need = ended;
+        } else {
+            bool fin = ended;            // a whole sequence ends here
+            uint32_t sid = id;           // its original index
+            int replay = -1;             // its record, if split
+            uint32_t replay_off = 0;     // where its rescoring starts
+            if (__any(ended && (id & kSegBit))) {
+                const bool seg = ended && (id & kSegBit);
+                int last = 0, m = mx, rec = 0;
+                uint32_t s = id, hot = 0;
+                if (seg && gstart) last = combine(m, s, rec, hot) ? 1 : 0;
+                // the group decides a replay together: broadcast from its
+                // first lane (0 in the other lanes; the offset compared
+                // as unsigned by flipping its sign bit)
+                last = group_max<G>(last);
+                int cmb = group_max<G>(gstart ? m : 0);
+                int pid = group_max<G>(gstart ? (int)s : 0);
+                rec = group_max<G>(gstart ? rec : 0);
+                uint32_t hb = (uint32_t)group_max<G>((int)((gstart ? hot : 0u) ^ 0x80000000u));
+                if (seg) {
+                    fin = last != 0;
+                    mx = cmb;
+                    sid = (uint32_t)pid;
+                    replay = rec;
+                    replay_off = hb ^ 0x80000000u;
+                }
+            }
             bool of = ovf || mx >= 255 - dbias;
             // the J state may have opened: replay in exact mode
-            redo = ended && !exact && !of && mx > kBase + kTec;
-        }
-        if (ended && !redo && gstart) {
-            if constexpr (MODE == kSSV) {
-                bool of = mx >= 255;
-                a.score[id] = of ? (uint8_t)127 : (uint8_t)(int8_t)(mx - 128);
-                a.flag[id] = of ? 1 : 0;
-            } else {
-                bool of = ovf || mx >= 255 - dbias;
+            bool redo = fin && !exact && !of && mx > kBase + kTec;
+            if (fin && !redo && gstart) {
                 int v = mx - kTec;
-                a.score[id] = of ? 255 : (uint8_t)(v < 0 ? 0 : v);
-                a.flag[id] = of ? 1 : 0;
+                a.score[sid] = of ? 255 : (uint8_t)(v < 0 ? 0 : v);
+                a.flag[sid] = of ? 1 : 0;
             }
-        }
-        if constexpr (MSV) {
             if (redo) {
+                // a split sequence is rescored from its own record, starting
+                // at its first hot segment
+                if (replay >= 0) {
+                    uint4 h, f;
+                    h = recs[2 * replay];
+                    f = recs[2 * replay + 1];
+                    start_record(h, f, true);
+                    seq_off = replay_off;
+                }
                 exact = true;
                 start_sequence();
                 load_words(seq_off, wv);
             }
+            need = ended && !redo;
         }
-        need = ended && !redo;
     }
+}
+
+// Segment records and slot of split sequence t (one thread each).
+__device__ __forceinline__ void build_segments(const KArgs &a, int t) {
+    // its bin: the last with bin_t <= t (unrolled, so the kernel argument
+    // arrays are read at constant offsets)
+    int bt = 0, bp = 0, bv = 0;
+#pragma unroll
+    for (int b = 0; b < kMaxBins; ++b) {
+        if (b < a.nbins && a.bin_t[b] <= t) {
+            bt = a.bin_t[b];
+            bp = a.bin_p[b];
+            bv = a.bin_v[b];
+        }
+    }
+    const int p = bp + (t - bt) * bv;
+    const SeqRec &r = a.seqs[t];
+    const uint32_t rows = r.rt & kRowsMask;
+    const uint32_t T = (uint32_t)a.seg_rows;
+    for (int s = 0; s < bv; ++s) {
+        uint32_t beg = (uint32_t)s * T;
+        uint32_t end = beg + T < rows ? beg + T : rows;
+        uint32_t st = s == 0 ? 0u : beg - (uint32_t)a.warm;
+        uint32_t off = r.off + st;
+        uint4 w = *(const uint4 *)(a.res + off);
+        uint4 *d = (uint4 *)(a.segs + p + s);
+        d[0] = make_uint4(off, (end - st) | (r.rt & ~kRowsMask), kSegBit | (uint32_t)t, w.x);
+        d[1] = w;
+    }
+    uint4 *sl = (uint4 *)(a.slots + kSlotWords * t);
+    sl[0] = make_uint4((uint32_t)bv, 0u, r.id, (uint32_t)t);
+    sl[1] = make_uint4(0xffffffffu, 0u, 0u, 0u);
 }
 
 // LDS image of the profile (see Layout): for table row x, register q and
 // lane j, the dword holds slots (q + 2jQ, q + (2j+1)Q) as two fp16 scores, in
 // every copy of q's chunk.  Threads 0..3 reset the work-queue counters.  For
-// MSV, kRows extra blocks compute best[x] = max_k (dbias - cost_k(x)).
+// MSV, kRows extra blocks compute best[x] = max_k (dbias - cost_k(x)).  The
+// last blocks build the records and slots of split sequences.
 template <int G, int Q, bool MSV>
 __global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks) {
     using Lay = Layout<G, Q>;
     constexpr int RS = Lay::RS;
+    const int seg_block0 = image_blocks + (MSV ? kRows : 0);
+    if ((int)blockIdx.x >= seg_block0) {
+        int t = ((int)blockIdx.x - seg_block0) * 256 + (int)threadIdx.x;
+        if (t < a.nsplit) build_segments(a, t);
+        return;
+    }
     if ((int)blockIdx.x >= image_blocks) {
         // MSV: best[x] = max_k (dbias - cost_k(x)) for each table row x
         __shared__ int red[256];
@@ -672,8 +777,9 @@ hipError_t launch_filter(const KArgs &a, int wpb, int blocks, hipStream_t s) {
     constexpr int n = kRows * Layout<G, Q>::RS;
     constexpr int nb = (n + 255) / 256;
     if (wpb < 1 || wpb > kMaxWaves<G>) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((prep_kernel<G, Q, MSV>), dim3(nb + (MSV ? kRows : 0)), dim3(256), 0, s,
-                       a, nb);
+    const int seg_blocks = (a.nsplit + 255) / 256;
+    hipLaunchKernelGGL((prep_kernel<G, Q, MSV>), dim3(nb + (MSV ? kRows : 0) + seg_blocks),
+                       dim3(256), 0, s, a, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if constexpr (kMaxWaves<G> > 8) {

@@ -32,6 +32,7 @@ struct hmsv_db {
     uint32_t pad_off = 0;
     int device = 0;
     std::vector<int64_t> order;   // processing order -> original index
+    std::vector<int64_t> cum_rows; // rows run by records [0, t), t = 0..nseq
 };
 
 namespace {
@@ -106,6 +107,68 @@ hmsv_status check_plan(const hmsv_plan *pl, int M) {
     return HMSV_OK;
 }
 
+// Blocks of a call's launch: the plan's, or a persistent grid of the
+// resident maximum with no more wavefronts than there are lane groups'
+// worth of sequences.  0 on a device error.
+int grid_blocks(const KernelEntry *e, const hmsv_plan &plan, int64_t count) {
+    int blocks = plan.blocks;
+    if (blocks == 0) {
+        blocks = resident_blocks(e, plan.waves_per_block);
+        if (blocks <= 0) return 0;
+        int64_t groups_per_block = (int64_t)plan.waves_per_block * (64 / plan.G);
+        int64_t need = (count + groups_per_block - 1) / groups_per_block;
+        if (need < blocks) blocks = (int)need;
+    }
+    return blocks;
+}
+
+// Which sequences of a call's range [first, first + count) to split, for
+// ngroups lane groups and profile length M.  A launch ends no earlier than
+// its longest sequence, which one lane group runs at the speed of a
+// wavefront sharing its SIMD; sequences well above the mean work per group
+// (total rows / ngroups) are therefore cut into segments of about that
+// many rows.  Segments carry M - 1 warm-up rows (rounded up to 16), so
+// segments are at least four times that long, and their number is capped.
+void plan_split(const hmsv_db *db, int64_t first, int64_t count, int64_t ngroups, int M,
+                KArgs &a) {
+    a.nsplit = 0;
+    a.nsegs = 0;
+    a.nbins = 0;
+    a.warm = ((M - 1) + 15) & ~15;
+    a.seg_rows = 0;
+    const int64_t *cum = db->cum_rows.data() + first;
+    const int64_t total = cum[count] - cum[0];
+    if (ngroups <= 0 || count < 2) return;
+    int64_t T = std::max<int64_t>({total / ngroups, 4 * (int64_t)a.warm, 256});
+    T = (T + 15) & ~(int64_t)15;
+    for (; T < (int64_t)kRowsLimit; T *= 2) {
+        // split the sequences above 1.5 T (they come first: longest first)
+        const int64_t thr = T + T / 2;
+        int64_t ns = 0, segs = 0, bins = 0, prev_v = -1;
+        bool fits = true;
+        while (ns < count && cum[ns + 1] - cum[ns] > thr) {
+            int64_t v = (cum[ns + 1] - cum[ns] + T - 1) / T;
+            if (v != prev_v) {
+                if (bins == kMaxBins) { fits = false; break; }
+                a.bin_t[bins] = (int32_t)ns;
+                a.bin_p[bins] = (int32_t)segs;
+                a.bin_v[bins] = (int32_t)v;
+                ++bins;
+                prev_v = v;
+            }
+            segs += v;
+            ++ns;
+            if (ns > kMaxSplit || segs > kMaxSegs) { fits = false; break; }
+        }
+        if (!fits) continue;
+        a.nsplit = (int32_t)ns;
+        a.nsegs = (int32_t)segs;
+        a.nbins = (int32_t)bins;
+        a.seg_rows = (int32_t)T;
+        return;
+    }
+}
+
 hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db,
                          int64_t first, int64_t count,
                          uint8_t *score, uint8_t *flags, void *workspace,
@@ -128,7 +191,7 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
     if (first < 0 || count < 0 || first > db->nseq || count > db->nseq - first) return HMSV_EINVAL;
     if (count == 0) return HMSV_OK;
 
-    KArgs a;
+    KArgs a{};
     a.cost = prof->cost;
     a.sc = prof->sc;
     a.M = prof->M;
@@ -143,17 +206,14 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
     a.counter = (uint32_t *)workspace;
     a.image = (uint32_t *)((char *)workspace + kWsCounterBytes);
     a.best = (int32_t *)((char *)workspace + 64);
+    a.segs = (SeqRec *)((char *)workspace + kWsSegOff);
+    a.slots = (uint32_t *)((char *)workspace + kWsSlotOff);
     if (((uintptr_t)workspace & 255u) != 0) return HMSV_EINVAL;
 
-    int blocks = plan.blocks;
-    if (blocks == 0) {
-        blocks = resident_blocks(e, plan.waves_per_block);
-        if (blocks <= 0) return HMSV_EDEVICE;
-        // no more wavefronts than there are lane groups' worth of sequences
-        int64_t groups_per_block = (int64_t)plan.waves_per_block * (64 / plan.G);
-        int64_t need = (count + groups_per_block - 1) / groups_per_block;
-        if (need < blocks) blocks = (int)need;
-    }
+    const int blocks = grid_blocks(e, plan, count);
+    if (blocks <= 0) return HMSV_EDEVICE;
+    plan_split(db, first, count, (int64_t)blocks * plan.waves_per_block * (64 / plan.G),
+               prof->M, a);
     if (e->launch(a, plan.waves_per_block, blocks, stream) != hipSuccess) return HMSV_EDEVICE;
     return HMSV_OK;
 }
@@ -250,6 +310,7 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
                      [&](int64_t a, int64_t b) { return len[a] > len[b]; });
     std::vector<SeqRec> recs((size_t)nseq);
     uint64_t total = 0, rows = 0;
+    std::vector<int64_t> cum_rows((size_t)nseq + 1, 0);
     for (int64_t t = 0; t < nseq; ++t) {
         int64_t i = order[t];
         uint64_t r = (uint64_t)std::max<int64_t>(4, (len[i] + 3) & ~(int64_t)3);
@@ -262,6 +323,7 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
         // (narrow lane groups run 16 rows per step and read past the end)
         total += ((r + 15) & ~(uint64_t)15) + 16;
         rows += r;
+        cum_rows[(size_t)t + 1] = (int64_t)rows;
         if (total >= ((uint64_t)1 << 32) - 64) return HMSV_EUNSUPPORTED;
     }
     const uint32_t pad_off = (uint32_t)total;
@@ -283,6 +345,7 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
     db->pad_off = pad_off;
     try {
         db->order = order;
+        db->cum_rows = cum_rows;
     } catch (...) {
         delete db;
         return HMSV_ENOMEM;
@@ -343,7 +406,7 @@ size_t hmsv_plan_lds_bytes(int32_t G, int32_t Q) {
 }
 
 size_t hmsv_workspace_bytes(int64_t nseq) {
-    (void)nseq;   // fixed today; the argument lets the layout grow with the database
+    (void)nseq;   // fixed: split sequences and segments are capped per call
     return kWsBytes;
 }
 
@@ -372,6 +435,34 @@ hmsv_status hmsv_ssv_score_range(const hmsv_profile *prof, const hmsv_db *db, in
     if (count < 0) return HMSV_EINVAL;
     return score_common(0, prof, db, first, count, (uint8_t *)score, flags, workspace, plan,
                         stream);
+}
+
+hmsv_status hmsv_split_info(const hmsv_db *db, int64_t first, int64_t count, int32_t is_msv,
+                            int32_t M, const hmsv_plan *plan_in, int32_t *nsplit,
+                            int32_t *nsegs, int32_t *seg_rows) {
+    if (!db || !nsplit || !nsegs || !seg_rows) return HMSV_EINVAL;
+    if (M < 1) return HMSV_EINVAL;
+    if (M > HMSV_MAX_M) return HMSV_EUNSUPPORTED;
+    hmsv_plan plan;
+    hmsv_status st = plan_in ? HMSV_OK : hmsv_default_plan(is_msv ? 1 : 0, M, &plan);
+    if (st != HMSV_OK) return st;
+    if (plan_in) plan = *plan_in;
+    st = check_plan(&plan, M);
+    if (st != HMSV_OK) return st;
+    const KernelEntry *e = registry().find(is_msv ? 1 : 0, plan.G, plan.Q);
+    if (!e) return HMSV_ENOKERNEL;
+    if (count == -1 && first == 0) count = db->nseq;
+    if (first < 0 || count < 0 || first > db->nseq || count > db->nseq - first) return HMSV_EINVAL;
+    *nsplit = *nsegs = *seg_rows = 0;
+    if (count == 0) return HMSV_OK;
+    const int blocks = grid_blocks(e, plan, count);
+    if (blocks <= 0) return HMSV_EDEVICE;
+    KArgs a{};
+    plan_split(db, first, count, (int64_t)blocks * plan.waves_per_block * (64 / plan.G), M, a);
+    *nsplit = a.nsplit;
+    *nsegs = a.nsegs;
+    *seg_rows = a.seg_rows;
+    return HMSV_OK;
 }
 
 hmsv_status hmsv_db_order(const hmsv_db *db, int64_t *ids) {

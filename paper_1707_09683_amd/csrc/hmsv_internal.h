@@ -19,13 +19,27 @@ struct SeqRec {
     uint32_t rt;        // rows | tjb << 24: rows to run (length rounded up to a
                         // multiple of 4, at least 4, below kRowsLimit) and the
                         // length-model cost tjb(L) of its true length (< 256)
-    uint32_t id;        // index in the caller's original order
+    uint32_t id;        // index in the caller's original order; for a
+                        // segment of a split sequence, kSegBit | its slot
     uint32_t first;     // its first four residues
     uint32_t first16[4];  // its first sixteen residues
 };
 static_assert(sizeof(SeqRec) == 32, "records are two 16-byte loads");
 constexpr uint32_t kRowsMask = 0xffffffu;
 constexpr uint32_t kRowsLimit = 0xffffffu;    // rows must stay below
+constexpr uint32_t kSegBit = 0x80000000u;     // record is a segment (ids stay below 2^31)
+
+// Split sequences.  A call may cut its longest sequences into segments of
+// seg_rows rows, each preceded by `warm` rows of the sequence (warm >= M - 1)
+// so that every cell of the segment's own rows is exact: a cell depends only
+// on the M rows above it along its diagonal.  Segment records live in the
+// workspace; each split sequence has a slot of kSlotWords words there:
+// {segments left, combined maximum, original id, record, MSV: lowest
+// offset of a segment whose maximum passed base + tec}.
+constexpr int kMaxSegs = 32768;       // segment records per call
+constexpr int kMaxSplit = 16384;      // split sequences per call
+constexpr int kMaxBins = 32;          // distinct segment counts per call
+constexpr int kSlotWords = 8;
 
 struct KArgs {
     const uint8_t *cost;   // [32][M] MSV costs (device)
@@ -42,12 +56,31 @@ struct KArgs {
     uint32_t *counter;     // work-queue head, zeroed by the prep kernel
     uint32_t *image;       // LDS image of the profile (workspace), 16-byte aligned
     int32_t *best;         // MSV: per table row, max over nodes of dbias - cost (workspace)
+    // split sequences: records [0, nsplit) of the range are replaced by
+    // nsegs segment records (workspace), processed first
+    SeqRec *segs;          // [kMaxSegs] segment records (workspace)
+    uint32_t *slots;       // [kMaxSplit][kSlotWords] per split sequence (workspace)
+    int32_t nsplit;
+    int32_t nsegs;
+    int32_t seg_rows;      // rows per segment (multiple of 16)
+    int32_t warm;          // rows before a segment (multiple of 16, >= M - 1)
+    // Split sequence t has v = ceil(rows / seg_rows) segments, which take
+    // records p .. p + v - 1.  Records are longest first, so v only falls
+    // with t: bin b covers t >= bin_t[b] with v = bin_v[b] and
+    // p = bin_p[b] + (t - bin_t[b]) * v.
+    int32_t nbins;
+    int32_t bin_t[kMaxBins];
+    int32_t bin_p[kMaxBins];
+    int32_t bin_v[kMaxBins];
 };
 
 // Workspace layout: queue counters (bytes 0..63), the MSV per-residue best
-// scores (bytes 64..147), then the profile's LDS image from byte 256.
+// scores (bytes 64..147), the profile's LDS image from byte 256, then the
+// segment records and the split-sequence slots.
 constexpr size_t kWsCounterBytes = 256;
-constexpr size_t kWsBytes = kWsCounterBytes + 160 * 1024;
+constexpr size_t kWsSegOff = kWsCounterBytes + 160 * 1024;
+constexpr size_t kWsSlotOff = kWsSegOff + (size_t)kMaxSegs * sizeof(SeqRec);
+constexpr size_t kWsBytes = kWsSlotOff + (size_t)kMaxSplit * kSlotWords * 4;
 
 typedef hipError_t (*LaunchFn)(const KArgs &, int waves_per_block, int blocks,
                                hipStream_t);

@@ -132,6 +132,36 @@ def test_long_sequences(hm, filt, M):
         assert exp[1].sum() > 0
 
 
+@pytest.mark.parametrize("filt", ["msv", "ssv"])
+@pytest.mark.parametrize("M,G", [(16, 2), (48, 4), (130, 16), (400, 8)])
+def test_split_sequences(hm, filt, M, G):
+    """Twelve sequences of 6,000..30,000 residues among 4,000 of 20..200:
+    the long ones are cut into segments scored in parallel (checked with
+    split_info), with implants (hits, J loop, overflow) anywhere along them,
+    so segment boundaries cross hits and MSV rescoring of a split sequence
+    occurs."""
+    rng = np.random.default_rng(500 + M)
+    emis = synth.sample_emissions(rng, M)
+    long_db = _implanted_db(rng, emis, 12, 6000, 30000, 0.5)
+    _short_implants(rng, emis, long_db, 1.0)
+    short_db = _implanted_db(rng, emis, 4000, 20, 200, 0.05)
+    db = synth.Database(np.concatenate([long_db.res, short_db.res]),
+                        np.concatenate([long_db.offsets,
+                                        short_db.offsets[1:] + long_db.offsets[-1]]))
+    Q = -(-(M + 1) // (2 * G))
+    plan = hm.make_plan(G, Q, 4, 0, 64)
+    gdb = hm.Database(db.res, db.offsets)
+    ns, nseg, T = hm.split_info(filt, M, gdb, plan)
+    gdb.close()
+    print(f"case split {filt} M={M} G={G} Q={Q}: {ns} split into {nseg} x {T}", flush=True)
+    assert ns == 12 and nseg > 24, (ns, nseg, T)
+    exp = _oracle(filt, emis, db)
+    _assert_same(_gpu(hm, filt, emis, db, plan), exp, what=f"split {filt} M={M}")
+    if filt == "msv" and M >= 48:
+        assert exp[1][:12].sum() > 0                              # an overflow among them
+        assert int(((exp[0][:12] > 190) & (exp[1][:12] == 0)).sum()) > 0   # rescored
+
+
 def _short_implants(rng, emis, db, frac):
     """Overwrite 1..3 segments of 5..12 residues emitted by consecutive
     nodes of the profile into a fraction of the sequences: scores that open

@@ -22,7 +22,13 @@ I6  cell values only grow with scB, and scB stays at its start value until
     the running maximum passes base + tec.  So one pass with scB fixed gives
     the exact result when its running maximum stays <= base + tec or reaches
     the overflow threshold; only sequences in between need the pass with
-    per-row scB updates.
+    per-row scB updates;
+I7  a cell depends only on the M rows above it along its diagonal, so a
+    long target can be cut into segments, each run from `warm` >= M - 1 rows
+    before its first row with fresh cells: the maximum over the segments of
+    their running maxima (SSV, and MSV with scB fixed) is the target's, since
+    warm-up rows only see parts of their diagonals and so never exceed the
+    true cells.
 """
 import numpy as np
 
@@ -262,3 +268,120 @@ def test_ssv_kernel_reformulation_matches_oracle():
             assert model_ssv(prof, x) == exp
             nov += exp[1]
     assert nov > 3
+
+
+def model_split_max(prof, x, filt, T, warm, pad=4):
+    """I7: running maximum of a target run in segments of T rows, each with
+    `warm` rows before it (SSV cells, or MSV cells with scB fixed)."""
+    M = prof["M"]
+    L = len(x)
+    rows = list(x) + [20] * ((-L) % pad if L else pad)
+    R = len(rows)
+    if filt == "ssv":
+        add, floor = prof["sc"].astype(np.int64), -128
+    else:
+        add, floor = prof["bias"] - prof["cost"].astype(np.int64), 0
+    best = floor
+    for beg in range(0, R, T):
+        cells = np.full(M, floor, np.int64)
+        for r in rows[max(0, beg - warm):min(R, beg + T)]:
+            cells = np.maximum(floor, np.concatenate(([floor], cells[:-1])) + add[r])
+            best = max(best, int(cells.max()))
+    return best
+
+
+def test_split_targets_keep_the_running_max():
+    """I7 for both filters on random profiles and targets with hits, for
+    segment lengths from 4 rows up and the smallest warm-up M - 1; one row
+    less of warm-up must fail somewhere (the bound is tight)."""
+    rng = np.random.default_rng(25)
+    short_fails = 0
+    for trial in range(30):
+        M = int(rng.choice([2, 3, 16, 48]))
+        emis = synth.sample_emissions(rng, M)
+        prof = q.quantize(emis, synth.BG)
+        db = synth.random_db(rng, 6, 40, 300)
+        synth.implant(rng, db.res, db.offsets, [emis], 0.5)
+        for sidx in range(db.n):
+            x = db.seq(sidx)
+            for filt in ("ssv", "msv"):
+                whole = model_split_max(prof, x, filt, 1 << 20, 0)
+                for T in (4, 16, 52):
+                    assert model_split_max(prof, x, filt, T, M - 1) == whole, (trial, sidx, T)
+                    assert model_split_max(prof, x, filt, T, M + 7) == whole
+                    if M > 1:
+                        short_fails += model_split_max(prof, x, filt, T, M - 2) != whole
+            # the whole-target maximum is the kernels' pass-1 quantity
+            whole_ssv = model_split_max(prof, x, "ssv", 1 << 20, 0)
+            assert model_ssv(prof, x) == ((127, 1) if whole_ssv >= 127 else (whole_ssv, 0))
+    assert short_fails > 0
+
+
+def model_msv_split(prof, x, T, warm, pad=4):
+    """The kernels' MSV on a split target: each segment's pass-1 maximum
+    (I5 form, including the never-above-scB case), combined by max; an exact
+    pass only when the combined maximum lies in (base + tec, 255 - dbias),
+    and then only from the first segment whose own maximum passed base + tec
+    (scB cannot move earlier, and that segment's warm-up cells stay below
+    the true ones)."""
+    bias = prof["bias"]
+    s = bias - prof["cost"].astype(np.int64)
+    best = s.max(axis=1)
+    L = len(x)
+    rows = list(x) + [20] * ((-L) % pad if L else pad)
+    R = len(rows)
+    tjbm = q.tjb(L) + prof["tbm"]
+    xb0 = max(0, q.BASE - tjbm)
+    c, hot = 0, None
+    for beg in range(0, R, T):
+        seg = rows[max(0, beg - warm):min(R, beg + T)]
+        W = np.zeros(prof["M"], np.int64)
+        run = 0
+        for r in seg:
+            W = np.maximum(0, np.concatenate(([0], W[:-1])) + s[r])
+            run = max(run, int(W.max()))
+        cs = run + xb0 if run > 0 else max(0, xb0 + int(max(best[r] for r in seg)))
+        c = max(c, cs)
+        if cs > q.BASE + q.tec() and hot is None:
+            hot = max(0, beg - warm)
+    if c >= 255 - bias:
+        return 255, 1
+    if c <= q.BASE + q.tec():
+        return max(0, c - q.tec()), 0
+    # exact pass (scB updated after every row) from the first hot segment's
+    # first warm-up row, with fresh cells and scB at its start value
+    tec, base = q.tec(), q.BASE
+    xb, cm, run, flag = xb0, -1, 0, False
+    W = np.zeros(prof["M"], np.int64)
+    for r in rows[hot:]:
+        W = np.maximum(0, np.concatenate(([0], W[:-1])) + s[r])
+        run = max(run, int(W.max()))
+        cc = max(cm, run + xb if run > 0 else -1)
+        if cc >= 255 - bias:
+            flag = True
+        xbn = max(0, max(base, cc - tec) - tjbm)
+        if xbn > xb:
+            W = np.maximum(0, W - (xbn - xb))
+            cm, run, xb = cc, 0, xbn
+    cc = max(cm, run + xb if run > 0 else -1)
+    if flag or cc >= 255 - bias:
+        return 255, 1
+    return max(0, cc - tec), 0
+
+
+def test_msv_split_matches_oracle():
+    rng = np.random.default_rng(26)
+    regimes = {"ovf": 0, "j": 0, "plain": 0}
+    for trial in range(30):
+        M = int(rng.choice([1, 3, 16, 48]))
+        emis = synth.sample_emissions(rng, M)
+        prof = q.quantize(emis, synth.BG)
+        db = synth.random_db(rng, 8, 0, 300)
+        synth.implant(rng, db.res, db.offsets, [emis], 0.4)
+        for sidx in range(db.n):
+            x = db.seq(sidx)
+            exp = oracle.msv_seq(prof, x)
+            for T in (4, 16, 64):
+                assert model_msv_split(prof, x, T, max(0, M - 1)) == exp, (trial, sidx, T)
+            regimes["ovf" if exp[1] else ("j" if exp[0] > q.BASE else "plain")] += 1
+    assert min(regimes.values()) > 3, regimes
