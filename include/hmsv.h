@@ -136,7 +136,7 @@ size_t hmsv_plan_lds_bytes(int32_t G, int32_t Q);
  * sequences (bytes): the work-queue counters, the MSV per-residue best
  * scores, the profile converted to the kernel's LDS layout, and the
  * records of split sequences' segments (at most 32768 segments of 16384
- * sequences per call; 1.4 MB in all). */
+ * sequences per call; about 2 MB in all). */
 size_t hmsv_workspace_bytes(int64_t nseq);
 
 /* ---- scoring -----------------------------------------------------------

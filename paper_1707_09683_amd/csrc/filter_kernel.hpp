@@ -568,65 +568,62 @@ filter_kernel(KArgs a) {
         } else {
             mx = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
         }
-        // A segment's maximum goes into its sequence's slot; the group that
-        // ends the last segment finishes the sequence with the maximum over
-        // all of them (every cell of the sequence lies in some segment's own
-        // rows, and a warm-up row's cells never exceed the true ones).  In
-        // the group's first lane: true if the sequence is finished, with m,
-        // s and rec replaced by its maximum, original index and record.
-        // MSV also keeps the offset of the first segment whose maximum
-        // passed base + tec (hot): scB cannot move before that segment's
-        // own rows, so a rescoring in exact mode can start at its first
+        // A split sequence's maximum is the maximum over its segments
+        // (every cell of the sequence lies in some segment's own rows, and
+        // a warm-up row's cells never exceed the true ones).  SSV segments
+        // store theirs for combine_kernel.  MSV segments combine here, in
+        // their sequence's slot, so that the group ending the last segment
+        // can rescore the sequence at once if its J state may have opened;
+        // the slot also keeps the offset of the first segment whose
+        // maximum passed base + tec (hot): scB cannot move before that
+        // segment's own rows, so the rescoring can start at its first
         // warm-up row with fresh cells (those rows' cells stay below the
         // true ones, hence below base + tec).
-        auto combine = [&](int &m, uint32_t &s, int &rec, uint32_t &hot) -> bool {
-            uint32_t *sl = a.slots + kSlotWords * (s & ~kSegBit);
-            atomicMax(sl + 1, (uint32_t)m);
-            if (MSV && m > kBase + kTec) atomicMin(sl + 4, seq_off);
-            __threadfence();
-            if (atomicSub(sl, 1u) != 1u) return false;
-            __threadfence();
-            m = (int)atomicMax(sl + 1, 0u);
-            if (MSV) hot = atomicMin(sl + 4, 0xffffffffu);
-            s = sl[2];
-            rec = (int)sl[3];
-            return true;
-        };
         if constexpr (MODE == kSSV) {
             if (ended && gstart) {
-                int m = mx, rec = 0;
-                uint32_t s = id, hot = 0;
-                if (!(id & kSegBit) || combine(m, s, rec, hot)) {
-                    bool of = m >= 255;
-                    a.score[s] = of ? (uint8_t)127 : (uint8_t)(int8_t)(m - 128);
-                    a.flag[s] = of ? 1 : 0;
+                if (id & kSegBit) {
+                    a.segx[2 * (id & ~kSegBit)] = (uint32_t)mx;
+                } else {
+                    bool of = mx >= 255;
+                    a.score[id] = of ? (uint8_t)127 : (uint8_t)(int8_t)(mx - 128);
+                    a.flag[id] = of ? 1 : 0;
                 }
             }
             need = ended;
         } else {
             bool fin = ended;            // a whole sequence ends here
-            uint32_t sid = id;           // its original index
+            uint32_t sid = id;           // its original index (first lane)
             int replay = -1;             // its record, if split
             uint32_t replay_off = 0;     // where its rescoring starts
             if (__any(ended && (id & kSegBit))) {
                 const bool seg = ended && (id & kSegBit);
-                int last = 0, m = mx, rec = 0;
-                uint32_t s = id, hot = 0;
-                if (seg && gstart) last = combine(m, s, rec, hot) ? 1 : 0;
-                // the group decides a replay together: broadcast from its
-                // first lane (0 in the other lanes; the offset compared
-                // as unsigned by flipping its sign bit)
+                uint32_t *sl = nullptr;
+                if (seg) sl = a.slots + kSlotWords * a.segx[2 * (id & ~kSegBit) + 1];
+                int last = 0;
+                if (seg && gstart) {
+                    atomicMax(sl + 1, (uint32_t)mx);
+                    if (mx > kBase + kTec) atomicMin(sl + 4, seq_off);
+                    __threadfence();
+                    if (atomicSub(sl, 1u) == 1u) {
+                        __threadfence();
+                        last = 1;
+                    }
+                }
+                // the group decides on a rescoring together: whether the
+                // first lane ended the last segment goes to every lane, which
+                // then reads the slot itself (at device scope, after the
+                // first lane's fence)
                 last = group_max<G>(last);
-                int cmb = group_max<G>(gstart ? m : 0);
-                int pid = group_max<G>(gstart ? (int)s : 0);
-                rec = group_max<G>(gstart ? rec : 0);
-                uint32_t hb = (uint32_t)group_max<G>((int)((gstart ? hot : 0u) ^ 0x80000000u));
                 if (seg) {
                     fin = last != 0;
-                    mx = cmb;
-                    sid = (uint32_t)pid;
-                    replay = rec;
-                    replay_off = hb ^ 0x80000000u;
+                    if (fin) {
+                        mx = (int)__hip_atomic_load(sl + 1, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+                        sid = sl[2];
+                        replay = (int)sl[3];
+                        replay_off = __hip_atomic_load(sl + 4, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                    }
                 }
             }
             bool of = ovf || mx >= 255 - dbias;
@@ -680,12 +677,31 @@ __device__ __forceinline__ void build_segments(const KArgs &a, int t) {
         uint32_t off = r.off + st;
         uint4 w = *(const uint4 *)(a.res + off);
         uint4 *d = (uint4 *)(a.segs + p + s);
-        d[0] = make_uint4(off, (end - st) | (r.rt & ~kRowsMask), kSegBit | (uint32_t)t, w.x);
+        d[0] = make_uint4(off, (end - st) | (r.rt & ~kRowsMask), kSegBit | (uint32_t)(p + s),
+                          w.x);
         d[1] = w;
+        a.segx[2 * (p + s) + 1] = (uint32_t)t;
     }
     uint4 *sl = (uint4 *)(a.slots + kSlotWords * t);
     sl[0] = make_uint4((uint32_t)bv, 0u, r.id, (uint32_t)t);
-    sl[1] = make_uint4(0xffffffffu, 0u, 0u, 0u);
+    sl[1] = make_uint4(0xffffffffu, (uint32_t)p, 0u, 0u);
+}
+
+// SSV: score and flag of each split sequence from its segments' maxima
+// (one thread each).
+static __global__ void __launch_bounds__(256) combine_kernel(KArgs a) {
+    const int t = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (t >= a.nsplit) return;
+    const uint32_t *sl = a.slots + kSlotWords * t;
+    const uint32_t v = sl[0], id = sl[2], p = sl[5];
+    uint32_t m = 0;
+    for (uint32_t k = 0; k < v; ++k) {
+        uint32_t x = a.segx[2 * (p + k)];
+        m = x > m ? x : m;
+    }
+    bool of = m >= 255;
+    a.score[id] = of ? (uint8_t)127 : (uint8_t)(int8_t)((int)m - 128);
+    a.flag[id] = of ? 1 : 0;
 }
 
 // LDS image of the profile (see Layout): for table row x, register q and
@@ -783,9 +799,14 @@ hipError_t launch_filter(const KArgs &a, int wpb, int blocks, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if constexpr (kMaxWaves<G> > 8) {
-        if (wpb > 8) return launch_filter_kernel<G, Q, MODE, 1024>(a, wpb, blocks, s);
+        if (wpb > 8) e = launch_filter_kernel<G, Q, MODE, 1024>(a, wpb, blocks, s);
+        else e = launch_filter_kernel<G, Q, MODE, 512>(a, wpb, blocks, s);
+    } else {
+        e = launch_filter_kernel<G, Q, MODE, 512>(a, wpb, blocks, s);
     }
-    return launch_filter_kernel<G, Q, MODE, 512>(a, wpb, blocks, s);
+    if (e != hipSuccess || MSV || a.nsplit == 0) return e;
+    hipLaunchKernelGGL(combine_kernel, dim3((a.nsplit + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 template <int G, int Q, int MODE, int THREADS>

@@ -208,6 +208,7 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
     a.best = (int32_t *)((char *)workspace + 64);
     a.segs = (SeqRec *)((char *)workspace + kWsSegOff);
     a.slots = (uint32_t *)((char *)workspace + kWsSlotOff);
+    a.segx = (uint32_t *)((char *)workspace + kWsSegxOff);
     if (((uintptr_t)workspace & 255u) != 0) return HMSV_EINVAL;
 
     const int blocks = grid_blocks(e, plan, count);

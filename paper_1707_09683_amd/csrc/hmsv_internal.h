@@ -20,7 +20,8 @@ struct SeqRec {
                         // multiple of 4, at least 4, below kRowsLimit) and the
                         // length-model cost tjb(L) of its true length (< 256)
     uint32_t id;        // index in the caller's original order; for a
-                        // segment of a split sequence, kSegBit | its slot
+                        // segment of a split sequence, kSegBit | its
+                        // index among the call's segments
     uint32_t first;     // its first four residues
     uint32_t first16[4];  // its first sixteen residues
 };
@@ -33,9 +34,13 @@ constexpr uint32_t kSegBit = 0x80000000u;     // record is a segment (ids stay b
 // seg_rows rows, each preceded by `warm` rows of the sequence (warm >= M - 1)
 // so that every cell of the segment's own rows is exact: a cell depends only
 // on the M rows above it along its diagonal.  Segment records live in the
-// workspace; each split sequence has a slot of kSlotWords words there:
-// {segments left, combined maximum, original id, record, MSV: lowest
-// offset of a segment whose maximum passed base + tec}.
+// workspace, with two words per segment {SSV: its maximum, its split
+// sequence}, and each split sequence has a slot of kSlotWords words:
+// {MSV: segments left, MSV: combined maximum, original id, record,
+// MSV: lowest offset of a segment whose maximum passed base + tec, first
+// segment, -, -}.  SSV segments store their maxima and a small kernel
+// combines them after the filter kernel; MSV combines in the filter
+// kernel, whose last segment decides on an exact rescoring.
 constexpr int kMaxSegs = 32768;       // segment records per call
 constexpr int kMaxSplit = 16384;      // split sequences per call
 constexpr int kMaxBins = 32;          // distinct segment counts per call
@@ -60,6 +65,7 @@ struct KArgs {
     // nsegs segment records (workspace), processed first
     SeqRec *segs;          // [kMaxSegs] segment records (workspace)
     uint32_t *slots;       // [kMaxSplit][kSlotWords] per split sequence (workspace)
+    uint32_t *segx;        // [kMaxSegs][2] per segment (workspace)
     int32_t nsplit;
     int32_t nsegs;
     int32_t seg_rows;      // rows per segment (multiple of 16)
@@ -80,7 +86,8 @@ struct KArgs {
 constexpr size_t kWsCounterBytes = 256;
 constexpr size_t kWsSegOff = kWsCounterBytes + 160 * 1024;
 constexpr size_t kWsSlotOff = kWsSegOff + (size_t)kMaxSegs * sizeof(SeqRec);
-constexpr size_t kWsBytes = kWsSlotOff + (size_t)kMaxSplit * kSlotWords * 4;
+constexpr size_t kWsSegxOff = kWsSlotOff + (size_t)kMaxSplit * kSlotWords * 4;
+constexpr size_t kWsBytes = kWsSegxOff + (size_t)kMaxSegs * 8;
 
 typedef hipError_t (*LaunchFn)(const KArgs &, int waves_per_block, int blocks,
                                hipStream_t);
