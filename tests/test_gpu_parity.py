@@ -132,6 +132,24 @@ def test_long_sequences(hm, filt, M):
         assert exp[1].sum() > 0
 
 
+@pytest.mark.parametrize("M,G", [(40, 2), (40, 16), (200, 4), (200, 8)])
+def test_msv_mostly_rescored(hm, M, G):
+    """Short implants in 90% of 2,000 sequences of 50..3,000 residues: about
+    a third of them open the J state without overflowing and are rescored
+    in exact mode (many per wavefront at once), half overflow."""
+    rng = np.random.default_rng(900 + M)
+    emis = synth.sample_emissions(rng, M)
+    db = synth.random_db(rng, 2000, 50, 3000)
+    _short_implants(rng, emis, db, 0.9)
+    Q = -(-(M + 1) // (2 * G))
+    print(f"case msv mostly rescored M={M} G={G}", flush=True)
+    exp = _oracle("msv", emis, db)
+    _assert_same(_gpu(hm, "msv", emis, db, hm.make_plan(G, Q, 4, 0, 64)), exp,
+                 what=f"M={M} G={G}")
+    assert int(((exp[0] > 190) & (exp[1] == 0)).sum()) > 400
+    assert int(exp[1].sum()) > 400
+
+
 @pytest.mark.parametrize("filt", ["msv", "ssv"])
 @pytest.mark.parametrize("M,G", [(16, 2), (48, 4), (130, 16), (400, 8)])
 def test_split_sequences(hm, filt, M, G):
