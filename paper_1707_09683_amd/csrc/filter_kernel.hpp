@@ -245,6 +245,15 @@ constexpr int kExitGroups = G == 1 ? 8 : G == 2 ? 4 : G == 4 ? 2 : 1;
 constexpr int kPipeQ = 17;
 constexpr int kPipeQMSV = 13;     // MSV also holds its exact-mode state
 
+// MSV groups of up to 4 lanes note the step in which a sequence's running
+// max passes base + tec, so a rescoring in exact mode starts there instead
+// of at the sequence's start.  Such plans serve short profiles, where the
+// J state opens often (scB starts closer to base); for the wider groups of
+// longer profiles the per-step check cost more than it saved (measured:
+// M = 64..192 2-18% faster, M = 400 and 768 1-1.5% slower).
+template <int G>
+constexpr bool kTrackHot = G <= 4;
+
 // Residue words (four residues each) per load and lane: 16 or 8 residues.
 template <int G>
 constexpr int kWordsPerLoad = G <= 8 ? 4 : 2;
@@ -301,6 +310,10 @@ filter_kernel(KArgs a) {
     uint32_t lvl = 0xffffffffu;  // MSV exact mode: check level (two u16 halves), all-ones = off
     bool exact = false;          // MSV: group replays its sequence in exact mode
     bool ovf = false;
+    // MSV, scB fixed: offset of the first step after which this lane's
+    // running max passed base + tec (kNoHot: none yet)
+    constexpr uint32_t kNoHot = 0xffffffffu;
+    uint32_t hot = kNoHot;
     bool active = false;
     bool need = false;           // group wants a sequence
     // Residues come in words of four, K words per load (16 residues for
@@ -397,16 +410,23 @@ filter_kernel(KArgs a) {
         int m = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
         return m > 0 ? m + xb : -1;
     };
-    // Exact mode: a cell above max(base + tec, built) moves scB; one at or
-    // above 255 - dbias overflows.  The check level is the larger relative
-    // cell value that does neither, as an fp16 pattern in both halves.
+    // A cell above max(base + tec, built) moves scB (exact mode); one at or
+    // above 255 - dbias overflows.  The level is the larger relative cell
+    // value that does neither, as an fp16 pattern in both halves.  With scB
+    // fixed (built = 0) it marks where the running max passes base + tec.
     auto set_level = [&]() {
         int lim = built > kBase + kTec ? built : kBase + kTec;
         int top = 254 - dbias;
         lim = lim < top ? lim : top;
         int rel = lim - xb;
         rel = rel < 0 ? 0 : rel;
-        lvl = (exact && !ovf) ? units_splat(rel) : 0xffffffffu;
+        lvl = ovf ? 0xffffffffu : units_splat(rel);
+    };
+    // any cell of this lane above the level?  (saturating u16 subtract)
+    auto above_level = [&]() -> bool {
+        return (uint32_t)__builtin_bit_cast(
+                   uint32_t, __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, st.xE),
+                                                           __builtin_bit_cast(u16x2, lvl))) != 0u;
     };
     auto start_sequence = [&]() {
         off = seq_off;
@@ -416,6 +436,7 @@ filter_kernel(KArgs a) {
         cm = -1;
         built = 0;
         ovf = false;
+        hot = kNoHot;
         set_level();
     };
 
@@ -502,10 +523,7 @@ filter_kernel(KArgs a) {
                     st.row(T, xrow(r));
                 }
                 if constexpr (MSV && decltype(check_c)::value) {
-                    // any cell above the level?  (saturating u16 subtract)
-                    bool hit = (uint32_t)__builtin_bit_cast(
-                        uint32_t, __builtin_elementwise_sub_sat(
-                            __builtin_bit_cast(u16x2, st.xE), __builtin_bit_cast(u16x2, lvl))) != 0u;
+                    const bool hit = exact && above_level();
                     if (__any(hit)) {
                         // Alg. 2 special states after this row, for every group
                         // whose running max passed its level (decided from the
@@ -541,6 +559,11 @@ filter_kernel(KArgs a) {
             // before the rows and its latency hides behind them.
 #pragma unroll
             for (int k = 0; k < K; ++k) asm volatile("" : "+v"(wn[k]));
+            if constexpr (MSV && kTrackHot<G>) {
+                // scB fixed: remember the step in which the running max
+                // first passed base + tec (a rescoring starts shortly before)
+                if (!exact && hot == kNoHot && above_level()) hot = off;
+            }
             off = offn;
             ended = active && off == (kExitGroups<G> > 1 ? a.pad_off : seq_end);
 #pragma unroll
@@ -594,15 +617,23 @@ filter_kernel(KArgs a) {
             bool fin = ended;            // a whole sequence ends here
             uint32_t sid = id;           // its original index (first lane)
             int replay = -1;             // its record, if split
-            uint32_t replay_off = 0;     // where its rescoring starts
+            // the group's first step that passed base + tec (unsigned min
+            // over its lanes, by a signed max of the flipped complement);
+            // called by whole wavefronts
+            auto group_hot = [&]() -> uint32_t {
+                return ~((uint32_t)group_max<G>((int)(~hot ^ 0x80000000u)) ^ 0x80000000u);
+            };
+            uint32_t replay_off = kNoHot;  // the rescoring starts shortly before
             if (__any(ended && (id & kSegBit))) {
                 const bool seg = ended && (id & kSegBit);
+                const uint32_t ghot = group_hot();
                 uint32_t *sl = nullptr;
                 if (seg) sl = a.slots + kSlotWords * a.segx[2 * (id & ~kSegBit) + 1];
                 int last = 0;
                 if (seg && gstart) {
                     atomicMax(sl + 1, (uint32_t)mx);
-                    if (mx > kBase + kTec) atomicMin(sl + 4, seq_off);
+                    // (without the per-step note, the segment's start)
+                    if (mx > kBase + kTec) atomicMin(sl + 4, ghot != kNoHot ? ghot : seq_off);
                     __threadfence();
                     if (atomicSub(sl, 1u) == 1u) {
                         __threadfence();
@@ -629,21 +660,33 @@ filter_kernel(KArgs a) {
             bool of = ovf || mx >= 255 - dbias;
             // the J state may have opened: replay in exact mode
             bool redo = fin && !exact && !of && mx > kBase + kTec;
+            if (__any(redo && replay < 0)) {
+                const uint32_t ghot = group_hot();
+                if (replay < 0) replay_off = ghot;
+            }
             if (fin && !redo && gstart) {
                 int v = mx - kTec;
                 a.score[sid] = of ? 255 : (uint8_t)(v < 0 ? 0 : v);
                 a.flag[sid] = of ? 1 : 0;
             }
             if (redo) {
-                // a split sequence is rescored from its own record, starting
-                // at its first hot segment
+                // Rescore in exact mode from `warm` (>= M - 1) rows before
+                // the first step whose running max passed base + tec (over
+                // all segments of a split sequence).  Before that step scB
+                // never moved, so fresh cells from there are exact from the
+                // step on, and the rows skipped or warmed up stay at or
+                // below base + tec (warm-up cells see parts of their
+                // diagonals only).  A split sequence starts from its own
+                // record.
                 if (replay >= 0) {
                     uint4 h, f;
                     h = recs[2 * replay];
                     f = recs[2 * replay + 1];
                     start_record(h, f, true);
-                    seq_off = replay_off;
                 }
+                const uint32_t w = (uint32_t)a.warm;
+                if (replay_off != kNoHot && replay_off >= seq_off + w)
+                    seq_off = (replay_off - w) & ~15u;
                 exact = true;
                 start_sequence();
                 load_words(seq_off, wv);
