@@ -385,3 +385,68 @@ def test_msv_split_matches_oracle():
                 assert model_msv_split(prof, x, T, max(0, M - 1)) == exp, (trial, sidx, T)
             regimes["ovf" if exp[1] else ("j" if exp[0] > q.BASE else "plain")] += 1
     assert min(regimes.values()) > 3, regimes
+
+
+def model_msv_rescore_from_step(prof, x, step, warm, pad=4):
+    """MSV as groups of up to 4 lanes run it: pass 1 with scB fixed notes
+    the first step (of `step` rows) after which the running max passed
+    base + tec; an exact pass, if needed, starts `warm` rows before that
+    step (rounded down to 16 rows) with fresh cells."""
+    bias = prof["bias"]
+    s = bias - prof["cost"].astype(np.int64)
+    best = s.max(axis=1)
+    L = len(x)
+    rows = list(x) + [20] * ((-L) % pad if L else pad)
+    tjbm = q.tjb(L) + prof["tbm"]
+    tec, base = q.tec(), q.BASE
+    xb0 = max(0, base - tjbm)
+    W = np.zeros(prof["M"], np.int64)
+    run, hot = 0, None
+    for i, r in enumerate(rows):
+        W = np.maximum(0, np.concatenate(([0], W[:-1])) + s[r])
+        run = max(run, int(W.max()))
+        if (i + 1) % step == 0 or i + 1 == len(rows):
+            if hot is None and run > 0 and run + xb0 > base + tec:
+                hot = (i // step) * step                  # the step's first row
+    c = run + xb0 if run > 0 else max(0, xb0 + int(max(best[r] for r in rows)))
+    if c >= 255 - bias:
+        return 255, 1
+    if c <= base + tec:
+        return max(0, c - tec), 0
+    b = hot - warm if hot >= warm else 0
+    b -= b % 16
+    xb, cm, run, flag = xb0, -1, 0, False
+    W = np.zeros(prof["M"], np.int64)
+    for r in rows[b:]:
+        W = np.maximum(0, np.concatenate(([0], W[:-1])) + s[r])
+        run = max(run, int(W.max()))
+        cc = max(cm, run + xb if run > 0 else -1)
+        if cc >= 255 - bias:
+            flag = True
+        xbn = max(0, max(base, cc - tec) - tjbm)
+        if xbn > xb:
+            W = np.maximum(0, W - (xbn - xb))
+            cm, run, xb = cc, 0, xbn
+    cc = max(cm, run + xb if run > 0 else -1)
+    if flag or cc >= 255 - bias:
+        return 255, 1
+    return max(0, cc - tec), 0
+
+
+def test_msv_rescore_from_step_matches_oracle():
+    rng = np.random.default_rng(27)
+    late = 0
+    for trial in range(30):
+        M = int(rng.choice([1, 3, 16, 48]))
+        emis = synth.sample_emissions(rng, M)
+        prof = q.quantize(emis, synth.BG)
+        db = synth.random_db(rng, 8, 0, 400)
+        synth.implant(rng, db.res, db.offsets, [emis], 0.4)
+        for sidx in range(db.n):
+            x = db.seq(sidx)
+            exp = oracle.msv_seq(prof, x)
+            for step in (8, 16):
+                got = model_msv_rescore_from_step(prof, x, step, max(0, M - 1))
+                assert got == exp, (trial, sidx, step)
+            late += exp[1] == 0 and exp[0] > q.BASE and len(x) > 100
+    assert late > 3
