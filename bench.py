@@ -118,7 +118,8 @@ def nthreads(a):
 
 
 def time_plain(hm, torch, filt, prof, gdb, plan, steps, warmup):
-    """Mean wall time per step (back-to-back) and mean HIP-event time per step."""
+    """Mean wall time per step (back-to-back), mean and median HIP-event time
+    per step."""
     dev = prof.device
     fn = hm.msv_score if filt == "msv" else hm.ssv_score
     sdt = torch.uint8 if filt == "msv" else torch.int8
@@ -138,8 +139,10 @@ def time_plain(hm, torch, filt, prof, gdb, plan, steps, warmup):
         e.record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t1) / steps
-    kern = float(np.mean([s.elapsed_time(e) for s, e in ev])) * 1e-3
-    return wall, kern, score, flags
+    times = [s.elapsed_time(e) for s, e in ev]
+    kern = float(np.mean(times)) * 1e-3
+    kern_median = float(np.median(times)) * 1e-3
+    return wall, kern, kern_median, score, flags
 
 
 def headline(a, hm, torch, synth):
@@ -158,11 +161,12 @@ def headline(a, hm, torch, synth):
     prof = hm.Profile.from_emissions(emis, synth.BG, dev)
     plan = hm.plan_for(a.filter, a.M) if not a.plan else \
         hm.make_plan(*[int(v) for v in a.plan.split(",")])
-    wall, kern, score, flags = time_plain(hm, torch, a.filter, prof, gdb, plan, a.steps,
-                                          a.warmup)
+    wall, kern, kern_median, score, flags = time_plain(hm, torch, a.filter, prof, gdb, plan,
+                                                       a.steps, a.warmup)
     cells = a.M * db.residues
     return {"workload": wname, "db": db, "gdb": gdb, "emis": emis, "plan": plan,
-            "wall": wall, "kern": kern, "cells": cells, "gen_s": gen_s,
+            "wall": wall, "kern": kern, "kern_median": kern_median, "cells": cells,
+            "gen_s": gen_s,
             "score": score.cpu().numpy(), "flags": flags.cpu().numpy()}
 
 
@@ -189,7 +193,7 @@ def ssv_leg(a, hm, torch, synth, h):
         M = emis.shape[0]
         prof = hm.Profile.from_emissions(emis, synth.BG, h["gdb"].device)
         plan = hm.plan_for("ssv", M)
-        wall, kern, score, flags = time_plain(hm, torch, "ssv", prof, h["gdb"], plan, 10, 2)
+        wall, kern, _, score, flags = time_plain(hm, torch, "ssv", prof, h["gdb"], plan, 10, 2)
         cells = M * h["db"].residues
         bad, _ = oracle_check(a, "ssv", emis, h["db"], score.cpu().numpy(),
                               flags.cpu().numpy(), synth)
@@ -350,6 +354,7 @@ def main():
                      "frac": round(achieved / PEAK_INSTR, 4),
                      "traffic": traffic_for(h["workload"], h["plan"].as_tuple()),
                      "kernel_ms": round(kern * 1e3, 4),
+                     "kernel_ms_median": round(h["kern_median"] * 1e3, 4),
                      "instr_per_cell": INSTR_PER_CELL[a.filter],
                      "cell_ceiling_gcups": round(PEAK_INSTR / INSTR_PER_CELL[a.filter] / 1e9)},
         "cpu_baseline": cpu,
