@@ -54,6 +54,22 @@ int32_t hmsv_tbm(int32_t M);
  * L >= 0.  Returns -1 for L < 0. */
 int32_t hmsv_tjb(int64_t L);
 
+/* ---- scores in nats (host) ---------------------------------------------
+ * Raw 8-bit scores as log-odds in nats, for ranking and thresholds (not
+ * bit-exact; P-values need a calibration the paper does not give).  The
+ * filters count in third-bits (s = 3 / ln 2 units per nat) and their raw
+ * scores still carry the length-model and entry costs (paper Sec. 2.1
+ * defers these units to HMMER3):
+ *   MSV: (raw - tjb(L) - base) / s - 3
+ *   SSV: (raw + 128 - tbm(M) - 2 tjb(L) - tec) / s - 3
+ * where the final 3 nats stand for the N/C/J length loops.  A sequence
+ * with flags[i] = 1 (saturated) gets +infinity.
+ * score: host, n raw scores (uint8_t for MSV, int8_t for SSV); flags,
+ * lengths (residues per sequence, >= 0) and nats: host, n entries.  Fails
+ * with HMSV_EINVAL on a null pointer, n < 0, M < 1 or a negative length. */
+hmsv_status hmsv_score_nats(int32_t is_msv, int32_t M, const void *score, const uint8_t *flags,
+                            const int64_t *lengths, int64_t n, double *nats);
+
 /* ---- quantization (host) ----------------------------------------------
  * Turns per-node match emission probabilities into the 8-bit tables of the
  * MSV (Alg. 2 sigma/dbias) and SSV (Alg. 7) kernels:

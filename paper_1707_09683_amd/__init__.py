@@ -94,6 +94,8 @@ for _f in ("hmsv_msv_score_range", "hmsv_ssv_score_range"):
                                   ctypes.POINTER(Plan), _P]
 _lib.hmsv_db_order.restype = ctypes.c_int
 _lib.hmsv_db_order.argtypes = [_P, _P]
+_lib.hmsv_score_nats.restype = ctypes.c_int
+_lib.hmsv_score_nats.argtypes = [_i32, _i32, _P, _P, _P, _i64, _P]
 _lib.hmsv_split_info.restype = ctypes.c_int
 _lib.hmsv_split_info.argtypes = [_P, _i64, _i64, _i32, _i32, ctypes.POINTER(Plan),
                                  ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
@@ -104,7 +106,7 @@ EXPORTED = ("hmsv_strerror", "hmsv_tbm", "hmsv_tjb", "hmsv_quantize", "hmsv_db_c
             "hmsv_msv_score", "hmsv_ssv_score",
             "hmsv_batch_create", "hmsv_batch_launch", "hmsv_batch_destroy",
             "hmsv_msv_score_range", "hmsv_ssv_score_range", "hmsv_db_order",
-            "hmsv_split_info")
+            "hmsv_split_info", "hmsv_score_nats")
 
 
 def _check(rc: int, what: str):
@@ -289,6 +291,23 @@ def msv_score(profile, db, score=None, flags=None, workspace=None, plan=None, st
 def ssv_score(profile, db, score=None, flags=None, workspace=None, plan=None, stream=None):
     """SSV filter (paper Alg. 7): int8 scores and overflow flags per sequence."""
     return _score("ssv", profile, db, score, flags, workspace, plan, stream)
+
+
+def score_nats(filt, M, score, flags, lengths):
+    """Raw scores as log-odds in nats (overflow: +inf); host arrays, one
+    entry per sequence, lengths in residues (see hmsv_score_nats)."""
+    sc = np.ascontiguousarray(score)
+    if sc.dtype.itemsize != 1:
+        raise TypeError("scores are one byte each")
+    sc = sc.view(np.uint8 if filt == "msv" else np.int8)
+    fl = np.ascontiguousarray(flags, dtype=np.uint8)
+    ln = np.ascontiguousarray(lengths, dtype=np.int64)
+    if not (sc.size == fl.size == ln.size):
+        raise ValueError("score, flags and lengths must have one entry per sequence")
+    out = np.empty(sc.size, dtype=np.float64)
+    _check(_lib.hmsv_score_nats(1 if filt == "msv" else 0, int(M), _np_ptr(sc), _np_ptr(fl),
+                                _np_ptr(ln), sc.size, _np_ptr(out)), "hmsv_score_nats")
+    return out
 
 
 def split_info(filt, M, db, plan=None, first=0, count=-1):

@@ -254,6 +254,27 @@ int32_t hmsv_tjb(int64_t L) {
     return third_bit_cost(3.0 / ((double)L + 3.0));
 }
 
+hmsv_status hmsv_score_nats(int32_t is_msv, int32_t M, const void *score, const uint8_t *flags,
+                            const int64_t *lengths, int64_t n, double *nats) {
+    if (n < 0 || M < 1) return HMSV_EINVAL;
+    if (n > 0 && (!score || !flags || !lengths || !nats)) return HMSV_EINVAL;
+    const double units_per_nat = 3.0 / std::log(2.0);
+    const int32_t tbm = hmsv_tbm(M);
+    for (int64_t i = 0; i < n; ++i) {
+        if (lengths[i] < 0) return HMSV_EINVAL;
+        if (flags[i]) {
+            nats[i] = HUGE_VAL;
+            continue;
+        }
+        const int32_t tjb = hmsv_tjb(lengths[i]);
+        const double u = is_msv
+            ? (double)((const uint8_t *)score)[i] - tjb - HMSV_BASE
+            : (double)((const int8_t *)score)[i] + 128.0 - tbm - 2.0 * tjb - HMSV_TEC;
+        nats[i] = u / units_per_nat - 3.0;
+    }
+    return HMSV_OK;
+}
+
 hmsv_status hmsv_quantize(const double *emis, const double *bg, int32_t M, uint8_t *cost,
                           int8_t *sc, int32_t *dbias) {
     if (!emis || !bg || !cost || !sc || !dbias) return HMSV_EINVAL;

@@ -5,6 +5,7 @@ reject bad arguments on the host before touching the device.  Its own
 quantizer and length-model constants are compared with the oracle's
 (independent implementations of the same definitions)."""
 import ctypes
+import math
 import os
 import re
 
@@ -132,3 +133,22 @@ def test_plan_lds_bytes():
         for M in (1, 48, 63, 64, 127, 128, 400, 1000, 2400, 3839):
             p = hm.default_plan(filt, M)
             assert 0 < hm.plan_lds_bytes(p.G, p.Q) <= 160 * 1024
+
+
+def test_score_nats():
+    """Raw scores in nats: third-bits (3 / ln 2 per nat) minus the length
+    and entry costs, 3 nats for the length loops, +inf on overflow.  Values
+    worked by hand with tjb(21) = 9, tjb(0) = 0 and tbm(48) = 31."""
+    ln2 = math.log(2.0)
+    got = hm.score_nats("msv", 48, np.array([199, 202, 255], np.uint8),
+                        np.array([0, 0, 1], np.uint8), np.array([21, 21, 21]))
+    assert got[0] == pytest.approx(-3.0, abs=1e-12)
+    assert got[1] == pytest.approx(ln2 - 3.0, abs=1e-12)
+    assert math.isinf(got[2]) and got[2] > 0
+    got = hm.score_nats("ssv", 48, np.array([100, -128], np.int8), np.array([0, 0], np.uint8),
+                        np.array([21, 0]))
+    assert got[0] == pytest.approx(176 * ln2 / 3 - 3.0, abs=1e-12)     # 100+128-31-18-3
+    assert got[1] == pytest.approx(-34 * ln2 / 3 - 3.0, abs=1e-12)     # -128+128-31-0-3
+    with pytest.raises(hm.HmsvError):
+        hm.score_nats("msv", 48, np.array([1], np.uint8), np.array([0], np.uint8),
+                      np.array([-1]))
