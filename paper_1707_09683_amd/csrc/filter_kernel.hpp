@@ -265,8 +265,10 @@ constexpr int kWordsPerLoad = G <= 8 ? 4 : 2;
 // Cells only grow with scB, and scB keeps that value until the running max
 // passes base + tec, so this result is exact when the running max stays at
 // or below base + tec (the J state never opens) or reaches the overflow
-// threshold.  Otherwise the group replays the sequence from its first row
-// in exact mode: after every row it checks (two instructions) whether any
+// threshold.  Otherwise the group replays the sequence in exact mode (from
+// its first row, or from shortly before the point where the running max
+// first passed base + tec where that is known: groups of up to 4 lanes,
+// split sequences): after every row it checks (two instructions) whether any
 // cell passed the level at which scB would change or overflow occurs, and
 // only then runs Alg. 2's special-state update (group max, new scB, cells
 // lowered by the rise).  Waves without a group in exact mode skip the check.
@@ -328,7 +330,7 @@ filter_kernel(KArgs a) {
     for (int k = 0; k < K; ++k) wv[k] = 0u;
 
     // Sequence pipeline (group-uniform).  While a group runs a sequence, the
-    // record of its next one (A, with A's first four residues stored in the
+    // record of its next one (A, with A's first sixteen residues stored in the
     // record) is loaded and the queue position after that (qc) is claimed.
     // At a switch: run A, load the record at qc as the new A, claim a new
     // qc.  The record load and the claim's atomic issued at a switch are
@@ -370,7 +372,7 @@ filter_kernel(KArgs a) {
         h = p[0];
         if constexpr (K > 1) f = p[1];
     };
-    uint4 ra;                    // record A: off, rows | tjb << 24, id, first word
+    uint4 ra;                    // record A: off, rows | tjb << 24, id, first residues
     uint4 ra16;                  // record A's first sixteen residues (K > 1)
     int qa, qc;                  // records of A and of the claimed position (kNone: none)
     uint32_t pend_b = 0;

@@ -22,7 +22,7 @@ struct SeqRec {
     uint32_t id;        // index in the caller's original order; for a
                         // segment of a split sequence, kSegBit | its
                         // index among the call's segments
-    uint32_t first;     // its first four residues
+    uint32_t first;     // its first four residues (also first16[0])
     uint32_t first16[4];  // its first sixteen residues
 };
 static_assert(sizeof(SeqRec) == 32, "records are two 16-byte loads");
