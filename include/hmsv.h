@@ -70,6 +70,16 @@ int32_t hmsv_tjb(int64_t L);
 hmsv_status hmsv_score_nats(int32_t is_msv, int32_t M, const void *score, const uint8_t *flags,
                             const int64_t *lengths, int64_t n, double *nats);
 
+/* P-values of scores in nats under a Gumbel null (paper Alg. 2 records a
+ * P-value at each sequence end; the location mu and scale lambda of the
+ * null distribution are a calibration the paper does not give, so the
+ * caller supplies them): P(S >= x) = 1 - exp(-exp(-lambda (x - mu))),
+ * computed without cancellation for large x; +infinity (overflow) gives 0.
+ * nats, p: host arrays of n entries.  Fails with HMSV_EINVAL on a null
+ * pointer, n < 0 or lambda <= 0. */
+hmsv_status hmsv_gumbel_pvalue(const double *nats, int64_t n, double mu, double lambda,
+                               double *p);
+
 /* ---- quantization (host) ----------------------------------------------
  * Turns per-node match emission probabilities into the 8-bit tables of the
  * MSV (Alg. 2 sigma/dbias) and SSV (Alg. 7) kernels:

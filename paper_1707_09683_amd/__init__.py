@@ -96,6 +96,8 @@ _lib.hmsv_db_order.restype = ctypes.c_int
 _lib.hmsv_db_order.argtypes = [_P, _P]
 _lib.hmsv_score_nats.restype = ctypes.c_int
 _lib.hmsv_score_nats.argtypes = [_i32, _i32, _P, _P, _P, _i64, _P]
+_lib.hmsv_gumbel_pvalue.restype = ctypes.c_int
+_lib.hmsv_gumbel_pvalue.argtypes = [_P, _i64, ctypes.c_double, ctypes.c_double, _P]
 _lib.hmsv_split_info.restype = ctypes.c_int
 _lib.hmsv_split_info.argtypes = [_P, _i64, _i64, _i32, _i32, ctypes.POINTER(Plan),
                                  ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
@@ -106,7 +108,7 @@ EXPORTED = ("hmsv_strerror", "hmsv_tbm", "hmsv_tjb", "hmsv_quantize", "hmsv_db_c
             "hmsv_msv_score", "hmsv_ssv_score",
             "hmsv_batch_create", "hmsv_batch_launch", "hmsv_batch_destroy",
             "hmsv_msv_score_range", "hmsv_ssv_score_range", "hmsv_db_order",
-            "hmsv_split_info", "hmsv_score_nats")
+            "hmsv_split_info", "hmsv_score_nats", "hmsv_gumbel_pvalue")
 
 
 def _check(rc: int, what: str):
@@ -307,6 +309,16 @@ def score_nats(filt, M, score, flags, lengths):
     out = np.empty(sc.size, dtype=np.float64)
     _check(_lib.hmsv_score_nats(1 if filt == "msv" else 0, int(M), _np_ptr(sc), _np_ptr(fl),
                                 _np_ptr(ln), sc.size, _np_ptr(out)), "hmsv_score_nats")
+    return out
+
+
+def gumbel_pvalue(nats, mu, lam):
+    """P-values of scores in nats under a Gumbel null with caller-supplied
+    location mu and scale lam (see hmsv_gumbel_pvalue)."""
+    x = np.ascontiguousarray(nats, dtype=np.float64)
+    out = np.empty(x.size, dtype=np.float64)
+    _check(_lib.hmsv_gumbel_pvalue(_np_ptr(x), x.size, float(mu), float(lam), _np_ptr(out)),
+           "hmsv_gumbel_pvalue")
     return out
 
 

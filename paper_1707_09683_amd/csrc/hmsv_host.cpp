@@ -275,6 +275,18 @@ hmsv_status hmsv_score_nats(int32_t is_msv, int32_t M, const void *score, const 
     return HMSV_OK;
 }
 
+hmsv_status hmsv_gumbel_pvalue(const double *nats, int64_t n, double mu, double lambda,
+                               double *p) {
+    if (n < 0 || !(lambda > 0.0)) return HMSV_EINVAL;
+    if (n > 0 && (!nats || !p)) return HMSV_EINVAL;
+    for (int64_t i = 0; i < n; ++i) {
+        const double y = -lambda * (nats[i] - mu);
+        // 1 - exp(-e^y) = -expm1(-e^y); e^y underflows to 0 for large scores
+        p[i] = -std::expm1(-std::exp(y));
+    }
+    return HMSV_OK;
+}
+
 hmsv_status hmsv_quantize(const double *emis, const double *bg, int32_t M, uint8_t *cost,
                           int8_t *sc, int32_t *dbias) {
     if (!emis || !bg || !cost || !sc || !dbias) return HMSV_EINVAL;

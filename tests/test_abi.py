@@ -152,3 +152,19 @@ def test_score_nats():
     with pytest.raises(hm.HmsvError):
         hm.score_nats("msv", 48, np.array([1], np.uint8), np.array([0], np.uint8),
                       np.array([-1]))
+
+
+def test_gumbel_pvalue():
+    """Gumbel survival 1 - exp(-exp(-lambda (x - mu))): 1 - 1/e at the
+    location, the exponential tail exp(-lambda (x - mu)) far above it
+    (computed without cancellation), 0 for +inf, and monotone."""
+    mu, lam = 2.5, 0.7
+    x = np.array([mu, mu + 60.0, mu - 3.0, np.inf, mu + 1.0])
+    p = hm.gumbel_pvalue(x, mu, lam)
+    assert p[0] == pytest.approx(1.0 - math.exp(-1.0), rel=1e-14)
+    assert p[1] == pytest.approx(math.exp(-lam * 60.0), rel=1e-9)
+    assert p[2] == pytest.approx(1.0 - math.exp(-math.exp(lam * 3.0)), rel=1e-14)
+    assert p[3] == 0.0
+    assert p[1] < p[4] < p[0] < p[2]
+    with pytest.raises(hm.HmsvError):
+        hm.gumbel_pvalue(x, mu, 0.0)
