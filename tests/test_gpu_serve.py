@@ -82,3 +82,36 @@ def test_range_calls_cover_database(env):
     assert sorted(order.tolist()) == list(range(gdb.nseq))
     L = db.lengths[order]
     assert (np.diff(L) <= 0).all()
+
+
+@pytest.mark.parametrize("filt", ["msv", "ssv"])
+def test_range_calls_split_long_sequences(env, filt):
+    """Ranges whose longest sequences are split into segments (a database
+    with 8,000..20,000-residue sequences among short ones, M = 48): every
+    range's results equal the oracle's, and the first range does split."""
+    hm, sv, rng, _db, _gdb = env
+    r = np.random.default_rng(77)
+    emis = synth.sample_emissions(r, 48)
+    long_db = synth.random_db(r, 6, 8000, 20000)
+    short_db = synth.random_db(r, 3000, 20, 300)
+    db = synth.Database(np.concatenate([long_db.res, short_db.res]),
+                        np.concatenate([long_db.offsets,
+                                        short_db.offsets[1:] + long_db.offsets[-1]]))
+    synth.implant(r, db.res, db.offsets, [emis], 0.2)
+    gdb = hm.Database(db.res, db.offsets)
+    prof = hm.Profile.from_emissions(emis, synth.BG)
+    sdt = torch.uint8 if filt == "msv" else torch.int8
+    s = torch.zeros(gdb.nseq, dtype=sdt, device="cuda")
+    f = torch.zeros(gdb.nseq, dtype=torch.uint8, device="cuda")
+    ws = hm.new_workspace(nseq=gdb.nseq)
+    edges = [0, 200, 1500, gdb.nseq]
+    plan = hm.plan_for(filt, 48)
+    assert hm.split_info(filt, 48, gdb, plan, 0, 200)[0] > 0
+    print(f"case range split {filt}", flush=True)
+    for a, b in zip(edges[:-1], edges[1:]):
+        hm.score_range(filt, prof, gdb, a, b - a, s, f, ws, plan)
+    torch.cuda.synchronize()
+    es, ef = oracle.score_db(filt, oq.quantize(emis, synth.BG), db.res, db.offsets)
+    gs = s.cpu().numpy().view(np.uint8 if filt == "msv" else np.int8)
+    assert np.array_equal(gs, es.view(gs.dtype)) and np.array_equal(f.cpu().numpy(), ef)
+    gdb.close()
