@@ -333,7 +333,10 @@ def main():
         extra["served"] = served_leg(a, hm, torch, synth)
 
     out = {
-        "metric": f"{a.filter.upper()} GCUPS at M={a.M} (bit-exact)",
+        # the default line carries the SSV and served legs beside the MSV value
+        "metric": ("MSV/SSV GCUPS at M=400 (bit-exact) + served p50/p99 latency vs plain launch"
+                   if (a.filter, a.M, a.no_extra) == ("msv", 400, False)
+                   else f"{a.filter.upper()} GCUPS at M={a.M} (bit-exact)"),
         "value": round(cells / wall / 1e9, 1),
         "unit": "GCUPS",
         "n_gpus": 1,
