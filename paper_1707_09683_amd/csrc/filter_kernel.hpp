@@ -599,11 +599,12 @@ filter_kernel(KArgs a) {
         // store theirs for combine_kernel.  MSV segments combine here, in
         // their sequence's slot, so that the group ending the last segment
         // can rescore the sequence at once if its J state may have opened;
-        // the slot also keeps the offset of the first segment whose
-        // maximum passed base + tec (hot): scB cannot move before that
-        // segment's own rows, so the rescoring can start at its first
-        // warm-up row with fresh cells (those rows' cells stay below the
-        // true ones, hence below base + tec).
+        // the slot also keeps the earliest offset at which a segment's
+        // running max passed base + tec (the step it happened in, for
+        // groups of up to 4 lanes, else the segment's start): scB cannot
+        // move before it, so the rescoring can start `warm` rows earlier
+        // with fresh cells (rows before that point stay at or below base +
+        // tec, and warm-up cells below the true ones).
         if constexpr (MODE == kSSV) {
             if (ended && gstart) {
                 if (id & kSegBit) {

@@ -37,8 +37,8 @@ constexpr uint32_t kSegBit = 0x80000000u;     // record is a segment (ids stay b
 // workspace, with two words per segment {SSV: its maximum, its split
 // sequence}, and each split sequence has a slot of kSlotWords words:
 // {MSV: segments left, MSV: combined maximum, original id, record,
-// MSV: lowest offset of a segment whose maximum passed base + tec, first
-// segment, -, -}.  SSV segments store their maxima and a small kernel
+// MSV: earliest offset at which a segment's running max passed base + tec,
+// first segment, -, -}.  SSV segments store their maxima and a small kernel
 // combines them after the filter kernel; MSV combines in the filter
 // kernel, whose last segment decides on an exact rescoring.
 constexpr int kMaxSegs = 32768;       // segment records per call
