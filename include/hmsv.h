@@ -186,7 +186,9 @@ size_t hmsv_workspace_bytes(int64_t nseq);
  * cells are exact (a cell depends only on the M rows above it along its
  * diagonal), and the sequence's maximum is the maximum over its segments.
  * An MSV sequence whose combined maximum shows the J state may have opened
- * is rescored whole, in order.  Scores are the same either way. */
+ * is rescored in order, in exact mode, from M - 1 rows (rounded up to 16)
+ * before the first point where its running max passed base + tec (scB
+ * cannot move earlier).  Scores are the same either way. */
 hmsv_status hmsv_msv_score(const hmsv_profile *prof, const hmsv_db *db,
                            uint8_t *score, uint8_t *flags, void *workspace,
                            const hmsv_plan *plan, hipStream_t stream);
