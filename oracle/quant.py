@@ -84,3 +84,18 @@ def quantize(emis: np.ndarray, bg: np.ndarray):
     sc = np.maximum(-128, bias - cost)
     return {"cost": cost.astype(np.uint8), "sc": sc.astype(np.int8), "bias": bias,
             "M": M, "tbm": tbm(M), "r": r}
+
+
+def from_costs(cost: np.ndarray, bias: int):
+    """A profile given directly by its 8-bit MSV cost table [32, M] and
+    offset ``bias`` (no emissions): the SSV table is derived as above,
+    ``sc = max(-128, bias - cost)``, and codes 20..31 cost 255 (-inf)
+    whatever the given rows 20..31 hold.  Same dict as ``quantize``."""
+    c = np.array(cost, dtype=np.int64)
+    if c.ndim != 2 or c.shape[0] != KP:
+        raise ValueError("cost must be [32, M]")
+    c[K:] = 255
+    M = c.shape[1]
+    sc = np.maximum(-128, int(bias) - c)
+    return {"cost": c.astype(np.uint8), "sc": sc.astype(np.int8), "bias": int(bias),
+            "M": M, "tbm": tbm(M)}

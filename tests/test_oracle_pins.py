@@ -120,6 +120,14 @@ def test_hand_worked_examples(case):
     name, prof, x, msv_exp, ssv_exp = case
     assert oracle.msv_seq(prof, x) == msv_exp
     assert oracle.ssv_seq(prof, x) == ssv_exp
+    # the same profile built from its cost table alone (rows 20..31 given
+    # as anything) scores the same
+    cost = prof["cost"].copy()
+    cost[20:] = 7
+    p2 = q.from_costs(cost, prof["bias"])
+    assert (p2["sc"] == prof["sc"]).all() and (p2["cost"][20:] == 255).all()
+    assert oracle.msv_seq(p2, x) == msv_exp
+    assert oracle.ssv_seq(p2, x) == ssv_exp
 
 
 # ----------------------------------------------------- independent checkers
@@ -330,3 +338,47 @@ def test_batch_driver_matches_single_calls():
         ids = np.array([5, 3, 99])
         s2, f2 = oracle.score_db(filt, prof, db.res, db.offsets, ids=ids)
         assert (s2[ids] == s[ids]).all() and (f2[ids] == f[ids]).all()
+
+
+# ------------------------------------------------------ nats and P-values
+
+def test_nats_hand_worked():
+    """Raw scores of the hand-worked fixture in nats (s = 3 / ln 2):
+    MSV two_node: 197 - tjb(3)=3 - 190 = 4 units -> 4 ln2 / 3 - 3;
+    SSV two_node: -110 + 128 - tbm(2)=5 - 2*3 - 3 = 4 units, the same;
+    the single best segment (10 + 8 = 18 units) pays the same entry and
+    length costs in both filters."""
+    from oracle import pvalue as pv
+    want = 4 * math.log(2) / 3 - 3
+    assert abs(pv.nats("msv", 197, 0, 3, 2) - want) < 1e-15
+    assert abs(pv.nats("ssv", -110, 0, 3, 2) - want) < 1e-15
+    assert pv.nats("msv", 255, 1, 3, 2) == math.inf
+    assert pv.nats("ssv", 127, 1, 3, 2) == math.inf
+    # base level: an MSV score of base + tjb is exactly -3 nats
+    assert pv.nats("msv", 190 + q.tjb(350), 0, 350, 400) == -3.0
+    # 3 units per bit: 3 more units is ln 2 nats more
+    d = pv.nats("ssv", 10, 0, 100, 48) - pv.nats("ssv", 7, 0, 100, 48)
+    assert abs(d - math.log(2)) < 1e-14
+
+
+def test_gumbel_closed_forms():
+    from oracle import pvalue as pv
+    mu, lam = -2.5, 0.69
+    # at the location, P = 1 - 1/e
+    assert abs(pv.gumbel_p(mu, mu, lam) - (1 - math.exp(-1))) < 1e-15
+    # far right tail: P ~ exp(-lambda (x - mu)) with relative error ~ y/2,
+    # y = exp(-lambda (x - mu))
+    for dx in (20.0, 40.0, 80.0):
+        y = math.exp(-lam * dx)
+        p = pv.gumbel_p(mu + dx, mu, lam)
+        assert abs(p / y - 1) < y
+    # far left tail: P -> 1
+    assert pv.gumbel_p(mu - 30, mu, lam) == 1.0
+    assert pv.gumbel_p(math.inf, mu, lam) == 0.0
+    # monotone, and the CDF identity against a direct evaluation where no
+    # cancellation occurs
+    xs = [mu - 3 + 0.5 * i for i in range(13)]
+    ps = [pv.gumbel_p(x, mu, lam) for x in xs]
+    assert all(a > b for a, b in zip(ps, ps[1:]))
+    for x, p in zip(xs, ps):
+        assert abs(p - (1 - math.exp(-math.exp(-lam * (x - mu))))) < 1e-12
