@@ -143,13 +143,22 @@ __device__ __forceinline__ uint32_t shift_in(uint32_t last) {
     return __builtin_amdgcn_alignbit(last, nb, 16);
 }
 
+// Score (filter units) added at node k (0-based) for table row x: MSV
+// dbias - cost, SSV sc.  Row kInvalidCode (every code 20..31, and the
+// padding rows) scores -inf whatever the caller's table holds there: cost
+// 255, sc -128.
+template <bool MSV>
+__device__ __forceinline__ int node_score(const KArgs &a, int x, int k) {
+    if (x == kInvalidCode) return MSV ? a.dbias - 255 : -128;
+    return MSV ? a.dbias - (int)a.cost[x * a.M + k] : (int)a.sc[x * a.M + k];
+}
+
 // fp16 pattern of the score added at slot s (node s, slot 0 = dummy) for
 // table row x.
 template <bool MSV>
 __device__ __forceinline__ uint32_t slot_bits(const KArgs &a, int x, int s) {
     if (s < 1 || s > a.M) return kMinus2;
-    int k = s - 1;
-    int v = MSV ? a.dbias - (int)a.cost[x * a.M + k] : (int)a.sc[x * a.M + k];
+    int v = node_score<MSV>(a, x, s - 1);
     _Float16 h = (_Float16)((float)v * (1.0f / 1024.0f));
     return (uint32_t)__builtin_bit_cast(unsigned short, h);
 }
@@ -771,7 +780,7 @@ __global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks) {
         int x = blockIdx.x - image_blocks;
         int m = -(1 << 30);
         for (int k = threadIdx.x; k < a.M; k += blockDim.x) {
-            int v = a.dbias - (int)a.cost[x * a.M + k];
+            int v = node_score<true>(a, x, k);
             m = v > m ? v : m;
         }
         red[threadIdx.x] = m;

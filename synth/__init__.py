@@ -126,6 +126,47 @@ def implant(rng, res: np.ndarray, offsets: np.ndarray, emis_list, frac: float = 
     return ids
 
 
+def random_cost_table(rng, M: int, dbias: int):
+    """A profile given directly as an 8-bit MSV cost table (no emissions).
+
+    Returns (cost uint8 [32, M], consensus uint8 [M]).  Every node has a
+    consensus residue scoring dbias - cost in 1..min(dbias, 10), or dbias
+    itself (cost 0) at 1.5% of the nodes, so a run of consensus residues along
+    a diagonal climbs in small steps with the odd jump.  The other residues
+    cost 2 or more above dbias (they score below zero), 5% of them 255.
+    Rows 20..31 are 255 (the non-scoring codes).  dbias in 0..255."""
+    cost = np.clip(dbias + 2 + np.rint(np.abs(rng.normal(0.0, 8.0, size=(K, M)))),
+                   0, 255).astype(np.int64)
+    cost[rng.random(size=(K, M)) < 0.05] = 255
+    cons = rng.integers(0, K, size=M)
+    gain = rng.integers(1, max(1, min(dbias, 10)) + 1, size=M)
+    gain[rng.random(M) < 0.015] = dbias
+    cost[cons, np.arange(M)] = np.maximum(0, dbias - gain)
+    full = np.full((KP, M), 255, dtype=np.uint8)
+    full[:K] = cost.astype(np.uint8)
+    return full, cons.astype(np.uint8)
+
+
+def implant_consensus(rng, res, offsets, consensus, frac: float, max_len: int,
+                      per_seq=(1, 3)):
+    """Overwrite 1..3 segments (``per_seq``) of a fraction of the sequences
+    with runs of consensus residues (``random_cost_table``): segment length
+    U{1..min(max_len, M, L)}, start node and position uniform.  Returns the
+    implanted sequence ids."""
+    M = len(consensus)
+    ids = np.flatnonzero(rng.random(len(offsets) - 1) < frac)
+    for sid in ids:
+        a, b = int(offsets[sid]), int(offsets[sid + 1])
+        if b == a:
+            continue
+        for _ in range(int(rng.integers(per_seq[0], per_seq[1] + 1))):
+            ln = int(rng.integers(1, min(max_len, M, b - a) + 1))
+            k0 = int(rng.integers(0, M - ln + 1))
+            p = a + int(rng.integers(0, b - a - ln + 1))
+            res[p:p + ln] = consensus[k0:k0 + ln]
+    return ids
+
+
 @dataclasses.dataclass
 class Database:
     res: np.ndarray       # uint8 codes, concatenated

@@ -450,3 +450,33 @@ def test_msv_rescore_from_step_matches_oracle():
                 assert got == exp, (trial, sidx, step)
             late += exp[1] == 0 and exp[0] > q.BASE and len(x) > 100
     assert late > 3
+
+
+def test_models_across_the_bias_range():
+    """The reformulations (I1..I7) hold over the whole accepted dbias range,
+    on profiles given directly as cost tables: dbias 0 (no cell ever rises
+    above scB), 20 and 40 (J state and overflow), 61..64 (overflow comes
+    before the running max can pass base + tec).  Sequences carry consensus
+    runs on random and on non-scoring backgrounds."""
+    rng = np.random.default_rng(28)
+    seen = {"ovf": 0, "j": 0, "plain": 0}
+    for dbias in (0, 20, 40, 61, 62, 63, 64):
+        for M in (1, 3, 16, 48):
+            cost, cons = synth.random_cost_table(rng, M, dbias)
+            prof = q.from_costs(cost, dbias)
+            db = synth.random_db(rng, 8, 0, 160)
+            synth.implant_consensus(rng, db.res, db.offsets, cons, 0.8, 24)
+            lad = synth.random_db(rng, 8, 1, 160)
+            lad.res[:] = 20
+            synth.implant_consensus(rng, lad.res, lad.offsets, cons, 1.0, 24, (1, 3))
+            for x in [db.seq(i) for i in range(db.n)] + [lad.seq(i) for i in range(lad.n)]:
+                exp = oracle.msv_seq(prof, x)
+                for tile in (4, 32):
+                    assert model_msv_w(prof, x, tile) == exp, (dbias, M, tile)
+                assert model_msv_two_pass(prof, x)[0] == exp, (dbias, M)
+                assert model_msv_split(prof, x, 16, max(0, M - 1)) == exp, (dbias, M)
+                assert model_msv_rescore_from_step(prof, x, 16, max(0, M - 1)) == exp, \
+                    (dbias, M)
+                assert model_ssv(prof, x) == oracle.ssv_seq(prof, x), (dbias, M)
+                seen["ovf" if exp[1] else ("j" if exp[0] > q.BASE else "plain")] += 1
+    assert min(seen.values()) > 10, seen
