@@ -98,10 +98,13 @@ hmsv_status hmsv_quantize(const double *emis, const double *bg, int32_t M,
 /* ---- profile ------------------------------------------------------------
  * A quantized profile whose tables live in caller-owned device memory.
  * cost (MSV) and sc (SSV) are [32][M] residue-major, as hmsv_quantize writes
- * them; rows 20..31 must all equal row 20 (non-scoring: 255 and -128).  The
- * library only reads them.  Either table may be NULL if that filter is not
- * used.  Preconditions checked on the host: 1 <= M <= HMSV_MAX_M and
- * 0 <= dbias <= HMSV_MAX_BIAS. */
+ * them.  Only rows 0..19 are read: codes 20..31 (and the kernels' padding
+ * rows) always score as -inf, i.e. cost 255 and sc -128, whatever the
+ * caller's rows 20..31 hold (hmsv_quantize writes exactly those values
+ * there).  The library only reads the tables.  Either table may be NULL if
+ * that filter is not used.  Preconditions checked on the host:
+ * 1 <= M <= HMSV_MAX_M and 0 <= dbias <= HMSV_MAX_BIAS.  MSV reads only
+ * cost (and dbias), SSV only sc. */
 typedef struct {
     int32_t M;
     int32_t dbias;
@@ -137,18 +140,24 @@ int64_t hmsv_db_padded_rows(const hmsv_db *db);  /* rows the kernels run */
  * -inf node).  64/G sequences share a wavefront (the paper's
  * multi-sequence alignment, Sec. 3.1 tier 4).  waves_per_block (1..8, or
  * 1..16 for G >= 32) wavefronts share one LDS copy of the profile;
- * blocks = 0 picks a persistent grid of the resident maximum.  tile is
- * kept for plan-table compatibility (a multiple of 4) and no longer
- * affects the kernels. */
+ * blocks = 0 picks a persistent grid of the resident maximum. */
 typedef struct {
     int32_t G;
     int32_t Q;
     int32_t waves_per_block;
     int32_t blocks;
-    int32_t tile;
 } hmsv_plan;
 
-/* The library's default plan for a filter ("msv" = 1, "ssv" = 0) and M. */
+/* The library's default plan for a filter ("msv" = 1, "ssv" = 0) and M: the
+ * autotuned plan (paper Sec. 3.4 chooses its kernel per model length).  A
+ * table of the plans measured fastest on MI355X (gfx950, 256 CUs) per
+ * filter and profile-length bin is compiled in; the bin nearest to M in
+ * log distance (ties to the smaller bin) whose group width G holds the
+ * profile in Q <= 32 registers per lane gives G and waves_per_block, and
+ * Q = ceil((M + 1) / 2G).  Lengths no tuned width can hold fall back to the
+ * narrowest group that can.  Host only; no device is queried.  Fails with
+ * HMSV_EINVAL on a null plan or M < 1, HMSV_EUNSUPPORTED for
+ * M > HMSV_MAX_M. */
 hmsv_status hmsv_default_plan(int32_t is_msv, int32_t M, hmsv_plan *plan);
 
 /* Bytes of LDS a plan's kernels hold per workgroup (the profile's image in
@@ -237,7 +246,7 @@ hmsv_status hmsv_db_order(const hmsv_db *db, int64_t *ids);
  * the same plan.
  * Each query owns its outputs and workspace (device, caller-owned, distinct
  * per query); score is uint8 for MSV, int8 for SSV.  plan.G == 0 selects
- * the library's default plan.  The batch keeps pointers, not copies, of
+ * the library's default (autotuned) plan.  The batch keeps pointers, not copies, of
  * the device buffers; the profile struct is copied.  branches: 1..16.
  * Fails with HMSV_EINVAL on bad arguments (including a workspace shared by
  * two queries), the errors of hmsv_*_score for a query, HMSV_EDEVICE if

@@ -48,17 +48,16 @@ class _CProfile(ctypes.Structure):
 
 class Plan(ctypes.Structure):
     """Launch plan (hmsv_plan): group width G, registers per lane Q,
-    waves per block, blocks (0 = persistent), tile (kept for ABI compatibility, unused)."""
+    waves per block, blocks (0 = persistent)."""
     _fields_ = [("G", ctypes.c_int32), ("Q", ctypes.c_int32),
-                ("waves_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32),
-                ("tile", ctypes.c_int32)]
+                ("waves_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32)]
 
     def __repr__(self):
         return (f"Plan(G={self.G}, Q={self.Q}, waves_per_block={self.waves_per_block}, "
-                f"blocks={self.blocks}, tile={self.tile})")
+                f"blocks={self.blocks})")
 
     def as_tuple(self):
-        return (self.G, self.Q, self.waves_per_block, self.blocks, self.tile)
+        return (self.G, self.Q, self.waves_per_block, self.blocks)
 
 
 _P = ctypes.c_void_p
@@ -210,25 +209,13 @@ def default_plan(filt: str, M: int) -> Plan:
     return p
 
 
-def make_plan(G, Q, waves_per_block=4, blocks=0, tile=64) -> Plan:
-    return Plan(int(G), int(Q), int(waves_per_block), int(blocks), int(tile))
-
-
-_tuned = None
+def make_plan(G, Q, waves_per_block=4, blocks=0) -> Plan:
+    return Plan(int(G), int(Q), int(waves_per_block), int(blocks))
 
 
 def plan_for(filt: str, M: int) -> Plan:
-    """The autotuned plan for this device (tuned_plans.json, nearest M-bin),
-    or the library's default plan when no tuned entry applies."""
-    global _tuned
-    from . import autotune
-    if _tuned is None:
-        table = autotune.load_table()
-        key = autotune.device_key() if table and torch.cuda.is_available() else None
-        _tuned = (table, key)
-    table, key = _tuned
-    t = autotune.lookup(table, key, filt, int(M)) if key else None
-    return make_plan(*t) if t else default_plan(filt, M)
+    """The library's default plan: the autotuned one (hmsv_default_plan)."""
+    return default_plan(filt, M)
 
 
 def plan_lds_bytes(G, Q) -> int:
@@ -339,3 +326,4 @@ def score_range(filt, profile, db, first, count, score, flags, workspace=None, p
     """Score positions [first, first+count) of the processing order (see
     Database.order) into the full-size score/flags tensors."""
     return _score(filt, profile, db, score, flags, workspace, plan, stream, (first, count))
+

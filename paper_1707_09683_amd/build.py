@@ -72,8 +72,20 @@ def _compile(cmd, out, stamp, incremental):
     return out, time.time() - t0, p.stderr
 
 
+def write_tuned_header() -> str:
+    """csrc/tuned_plans.inc from tuned_plans.json (autotune.py, loaded by
+    path: importing the package needs the library being built)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("hmsv_autotune",
+                                                  os.path.join(HERE, "autotune.py"))
+    at = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(at)
+    return at.write_header()
+
+
 def build(jobs: int | None = None, incremental: bool = False, verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
+    write_tuned_header()
     jobs = jobs or max(1, min(16, os.cpu_count() or 1))
     tasks = []
     host_obj = os.path.join(OBJ, "hmsv_host.o")
@@ -113,7 +125,7 @@ def resources(jobs: int | None = None) -> str:
     key = next(k for k in table if not k.startswith("_"))
     want = {}
     for filt in ("msv", "ssv"):
-        for M, (G, Q, wpb, _b, _t) in table[key][filt].items():
+        for M, (G, Q, wpb, _b) in table[key][filt].items():
             want.setdefault((filt, G, Q), []).append((int(M), wpb))
     units = sorted({(G, lo, hi) for _f, G, Q in want for (GG, lo, hi) in kernel_units()
                     if GG == G and lo <= Q <= hi})

@@ -61,19 +61,32 @@ Registry &registry() {
     return r;
 }
 
+// Launch plans the autotuner measured fastest on MI355X (gfx950, 256 CUs)
+// per filter and profile-length bin, compiled in from tuned_plans.json.
+struct TunedPlan { int is_msv; int bin; int G; int waves_per_block; };
+const TunedPlan kTuned[] = {
+#include "tuned_plans.inc"
+};
+constexpr int kNumTuned = (int)(sizeof(kTuned) / sizeof(kTuned[0]));
 
-// Persistent-grid size per (kernel, waves_per_block), measured once per device.
-struct OccKey { const KernelEntry *e; int wpb; int dev; };
+
+// Persistent-grid size per (kernel, waves_per_block), measured once per
+// device.  A fixed table (no allocation on the scoring path); when it is
+// full the figure is measured again at each call.
+struct OccEntry { const KernelEntry *e; int wpb; int dev; int blocks; };
+constexpr int kOccCap = 4096;
 std::mutex g_occ_mu;
-std::vector<std::pair<OccKey, int>> g_occ;
+OccEntry g_occ[kOccCap];
+int g_nocc = 0;
 
 int resident_blocks(const KernelEntry *e, int wpb) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     {
         std::lock_guard<std::mutex> lk(g_occ_mu);
-        for (auto &p : g_occ)
-            if (p.first.e == e && p.first.wpb == wpb && p.first.dev == dev) return p.second;
+        for (int i = 0; i < g_nocc; ++i)
+            if (g_occ[i].e == e && g_occ[i].wpb == wpb && g_occ[i].dev == dev)
+                return g_occ[i].blocks;
     }
     int per_cu = e->occupancy(wpb);
     int cus = 0;
@@ -81,7 +94,7 @@ int resident_blocks(const KernelEntry *e, int wpb) {
         return 0;
     int blocks = per_cu * cus;
     std::lock_guard<std::mutex> lk(g_occ_mu);
-    g_occ.push_back({{e, wpb, dev}, blocks});
+    if (g_nocc < kOccCap) g_occ[g_nocc++] = OccEntry{e, wpb, dev, blocks};
     return blocks;
 }
 
@@ -102,7 +115,6 @@ hmsv_status check_plan(const hmsv_plan *pl, int M) {
     if (pl->waves_per_block < 1 || pl->waves_per_block > (pl->G >= 32 ? 16 : 8))
         return HMSV_EINVAL;
     if (pl->blocks < 0) return HMSV_EINVAL;
-    if (pl->tile < 4 || (pl->tile % 4) != 0) return HMSV_EINVAL;
     if (lds_bytes(pl->G, pl->Q) > (size_t)kLdsBytes) return HMSV_EUNSUPPORTED;
     return HMSV_OK;
 }
@@ -416,19 +428,43 @@ hmsv_status hmsv_default_plan(int32_t is_msv, int32_t M, hmsv_plan *plan) {
     if (!plan) return HMSV_EINVAL;
     if (M < 1) return HMSV_EINVAL;
     if (M > HMSV_MAX_M) return HMSV_EUNSUPPORTED;
-    // Narrowest lane group whose registers (Q <= 32 per lane) still hold the
-    // profile: more sequences per wavefront and more cells per row of
-    // per-row overhead (measured best at M = 48, 400 and 2400).
+    // The autotuned plan (paper Sec. 3.4 picks its kernel per model length
+    // the same way): among the tuned M-bins of this filter, nearest to M in
+    // log distance first (ties to the smaller bin), the first whose group
+    // width still holds the profile within Q <= 32 registers and the LDS.
+    int idx[kNumTuned];
+    int n = 0;
+    for (int i = 0; i < kNumTuned; ++i)
+        if (kTuned[i].is_msv == (is_msv ? 1 : 0)) idx[n++] = i;
+    auto dist = [M](int b) { return std::fabs(std::log((double)b) - std::log((double)M)); };
+    std::stable_sort(idx, idx + n, [&](int a, int b) {
+        double da = dist(kTuned[a].bin), db = dist(kTuned[b].bin);
+        if (da != db) return da < db;
+        return kTuned[a].bin < kTuned[b].bin;
+    });
+    for (int t = 0; t < n; ++t) {
+        const TunedPlan &tp = kTuned[idx[t]];
+        int G = tp.G;
+        int Q = (M + 1 + 2 * G - 1) / (2 * G);
+        if (Q > 32 || lds_bytes(G, Q) > (size_t)kLdsBytes) continue;
+        if (!registry().find(is_msv ? 1 : 0, G, Q)) continue;
+        plan->G = G;
+        plan->Q = Q;
+        plan->waves_per_block = tp.waves_per_block;
+        plan->blocks = 0;
+        return HMSV_OK;
+    }
+    // Untuned fallback: the narrowest lane group whose registers (Q <= 32
+    // per lane) still hold the profile.
     for (int G : {1, 2, 4, 8, 16, 32, 64}) {
         int Q = (M + 1 + 2 * G - 1) / (2 * G);
         if (Q > 32 || lds_bytes(G, Q) > (size_t)kLdsBytes) continue;
-        if (!registry().find(is_msv, G, Q)) continue;
+        if (!registry().find(is_msv ? 1 : 0, G, Q)) continue;
         plan->G = G;
         plan->Q = Q;
         // large tables allow one block per CU: fill it with wavefronts
         plan->waves_per_block = lds_bytes(G, Q) > 48 * 1024 ? 8 : 4;
         plan->blocks = 0;
-        plan->tile = 64;
         return HMSV_OK;
     }
     return HMSV_ENOKERNEL;

@@ -106,9 +106,12 @@ def test_score_rejects_bad_arguments_before_launch():
     bad_plan = hm.make_plan(8, 2)                 # covers 31 < 100 nodes
     assert hm._lib.hmsv_msv_score(ctypes.byref(prof), ctypes.c_void_p(1), 1, 1, ws,
                                   ctypes.byref(bad_plan), None) == -1
-    odd_plan = hm.make_plan(8, 7, tile=6)         # tile not a multiple of 4
+    odd_plan = hm.make_plan(6, 9)                 # G not a power of two
     assert hm._lib.hmsv_msv_score(ctypes.byref(prof), ctypes.c_void_p(1), 1, 1, ws,
                                   ctypes.byref(odd_plan), None) == -1
+    many_waves = hm.make_plan(8, 7, waves_per_block=9)
+    assert hm._lib.hmsv_msv_score(ctypes.byref(prof), ctypes.c_void_p(1), 1, 1, ws,
+                                  ctypes.byref(many_waves), None) == -1
     assert hm._lib.hmsv_msv_score(ctypes.byref(prof), None, 1, 1, ws, None, None) == -1
 
 
@@ -119,6 +122,27 @@ def test_default_plans_cover_every_length():
             assert 2 * p.G * p.Q - 1 >= M and 64 % p.G == 0
     with pytest.raises(hm.HmsvError):
         hm.default_plan("msv", 3840)
+
+
+def test_default_plan_is_the_tuned_plan():
+    """The C library's default plan equals the autotuner's table
+    (tuned_plans.json, MI355X entry) looked up the documented way, at every
+    tuned M-bin and at lengths between and beyond them."""
+    from paper_1707_09683_amd import autotune
+    table = autotune.load_table()
+    key = autotune.DEVICE_KEY
+    assert key in table
+    for filt in ("msv", "ssv"):
+        bins = sorted(int(b) for b in table[key][filt])
+        Ms = set(bins) | {1, 2, 17, 29, 35, 44, 55, 70, 300, 450, 1100, 2222, 3500, 3839}
+        Ms |= {int(round((a * b) ** 0.5)) for a, b in zip(bins[:-1], bins[1:])}
+        for M in sorted(Ms):
+            exp = autotune.lookup(table, key, filt, M)
+            got = hm.default_plan(filt, M).as_tuple()
+            assert exp is not None and got == tuple(exp), (filt, M, got, exp)
+            assert hm.plan_for(filt, M).as_tuple() == got
+    # the compiled-in table is the one generated from the JSON
+    assert open(autotune.HEADER).read() == autotune.emit_header(table)
 
 
 def test_plan_lds_bytes():

@@ -68,7 +68,7 @@ def test_m48_every_group_width(hm, cfg0, filt, gq):
     emis = cfg0.emissions[0]
     G, Q = gq
     print(f"case m48 {filt} G={G} Q={Q}", flush=True)
-    plan = hm.make_plan(G, Q, waves_per_block=2, blocks=0, tile=8)
+    plan = hm.make_plan(G, Q, waves_per_block=2, blocks=0)
     _assert_same(_gpu(hm, filt, emis, cfg0.db, plan), _oracle(filt, emis, cfg0.db),
                  what=f"{filt} G{G} Q{Q}")
 
@@ -144,7 +144,7 @@ def test_msv_mostly_rescored(hm, M, G):
     Q = -(-(M + 1) // (2 * G))
     print(f"case msv mostly rescored M={M} G={G}", flush=True)
     exp = _oracle("msv", emis, db)
-    _assert_same(_gpu(hm, "msv", emis, db, hm.make_plan(G, Q, 4, 0, 64)), exp,
+    _assert_same(_gpu(hm, "msv", emis, db, hm.make_plan(G, Q, 4, 0)), exp,
                  what=f"M={M} G={G}")
     assert int(((exp[0] > 190) & (exp[1] == 0)).sum()) > 400
     assert int(exp[1].sum()) > 400
@@ -167,7 +167,7 @@ def test_split_sequences(hm, filt, M, G):
                         np.concatenate([long_db.offsets,
                                         short_db.offsets[1:] + long_db.offsets[-1]]))
     Q = -(-(M + 1) // (2 * G))
-    plan = hm.make_plan(G, Q, 4, 0, 64)
+    plan = hm.make_plan(G, Q, 4, 0)
     gdb = hm.Database(db.res, db.offsets)
     ns, nseg, T = hm.split_info(filt, M, gdb, plan)
     gdb.close()
