@@ -84,6 +84,7 @@ class Request:
         self.t_admit = None
         self.t_done = None
         self.future = cf.Future()
+        self.future.rid = rid             # lets a caller find the request's record
         self.chunks = []
         self.next_chunk = 0
         self.remaining = 0
@@ -111,7 +112,7 @@ class _Slot:
 class Server:
     def __init__(self, db: Database, bg, device="cuda", max_inflight=8, depth=2,
                  chunk_cells=2e11, hbm_budget=2 << 30, lds_budget=160 * 1024,
-                 poll_s=100e-6, aging=1.0, rate=3.0e13):
+                 poll_s=100e-6, aging=1.0, rate=3.0e13, keep_completed=256):
         self.db = db
         self.bg = np.asarray(bg, dtype=np.float64)
         self.device = torch.device(device)
@@ -141,7 +142,9 @@ class Server:
         self._cv = threading.Condition()
         self._stop = False
         self._rid = 0
-        self.completed = []
+        # the last keep_completed finished requests (timing fields and the
+        # future); their device tables are released at completion
+        self.completed = collections.deque(maxlen=keep_completed)
         self._thread = threading.Thread(target=self._loop, daemon=True)
         self._thread.start()
 
@@ -237,6 +240,7 @@ class Server:
             fl = r.slot.h_flags.numpy().copy()
             r.slot.busy = False
             r.slot = None
+            r.profile = None                  # the request's device tables
             self.completed.append(r)
             r.future.set_result((sc, fl))
 
@@ -282,6 +286,9 @@ def replay(server: Server, arrivals, filters, emissions):
         futs.append(server.submit(f, e, t_arrival=t0 + t))
     for fu in futs:
         fu.result()
-    reqs = sorted(server.completed[-len(futs):], key=lambda r: r.rid)
+    done = {r.rid: r for r in server.completed}
+    if any(fu.rid not in done for fu in futs):
+        raise RuntimeError("replay longer than the server keeps completed requests")
+    reqs = [done[fu.rid] for fu in futs]
     span = max(r.t_done for r in reqs) - t0
     return reqs, span
