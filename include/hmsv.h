@@ -168,10 +168,11 @@ hmsv_status hmsv_default_plan(int32_t is_msv, int32_t M, hmsv_plan *plan);
 size_t hmsv_plan_lds_bytes(int32_t G, int32_t Q);
 
 /* Device workspace needed by a scoring call on a database of nseq
- * sequences (bytes): the work-queue counters, the MSV per-residue best
- * scores, the profile converted to the kernel's LDS layout, and the
- * records of split sequences' segments (at most 32768 segments of 16384
- * sequences per call; about 2 MB in all). */
+ * sequences (bytes; pass the database's full sequence count, also for
+ * range calls): the work-queue counters, the MSV per-residue best scores,
+ * the profile converted to the kernel's LDS layout, the records of split
+ * sequences' segments (at most 32768 segments of 16384 sequences per call;
+ * about 2 MB), and 32 bytes per sequence for the MSV rescoring windows. */
 size_t hmsv_workspace_bytes(int64_t nseq);
 
 /* ---- scoring -----------------------------------------------------------
@@ -194,10 +195,13 @@ size_t hmsv_workspace_bytes(int64_t nseq);
  * M - 1 rows (rounded up to 16) before its own rows, so all of its own
  * cells are exact (a cell depends only on the M rows above it along its
  * diagonal), and the sequence's maximum is the maximum over its segments.
- * An MSV sequence whose combined maximum shows the J state may have opened
- * is rescored in order, in exact mode, from M - 1 rows (rounded up to 16)
- * before the first point where its running max passed base + tec (scB
- * cannot move earlier).  Scores are the same either way. */
+ * MSV runs every sequence with scB fixed first (exact unless the J state
+ * opens, Alg. 2); a second launch on the same stream rescores, with
+ * Alg. 2's special states after every row, only a window of each sequence
+ * whose running max passed base + tec: from M - 1 rows (rounded up to 16)
+ * before the first step of 8 or 16 rows in which a cell passed that level
+ * to the end of the last such step (scB can move only there).  Scores are
+ * the same either way. */
 hmsv_status hmsv_msv_score(const hmsv_profile *prof, const hmsv_db *db,
                            uint8_t *score, uint8_t *flags, void *workspace,
                            const hmsv_plan *plan, hipStream_t stream);

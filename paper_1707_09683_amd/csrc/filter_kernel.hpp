@@ -32,8 +32,9 @@
 //    banks: no bank conflicts between groups reading different rows.
 //  * Sequences are handed out longest first from a global counter as groups
 //    finish (replaces the pre-packed warp blocks of Alg. 1).
-//  * MSV special states: scB fixed first, exact replay when needed (see
-//    filter_kernel).  When scB rises by
+//  * MSV special states: scB fixed for every sequence first, then an exact
+//    rescoring of short windows of the few sequences where the J state may
+//    open, in a second launch (see filter_kernel).  When scB rises by
 //    d, every relative cell becomes max(u - d, 0); the running max of
 //    earlier scB values is kept as an integer.  A sequence whose cells never
 //    rise above scB has running max
@@ -235,14 +236,22 @@ struct Lane {
     }
 };
 
-// Kernel modes.
+// Kernel modes.  MSV runs as two launches: kMSV scores every sequence with
+// scB fixed and settles all but the few whose running max passes base + tec
+// (where the J state may open); kMSVX then rescores those in exact mode,
+// each over a short window of its rows.  Keeping the exact-mode code out of
+// the kernel that does almost all of the work keeps its register count at
+// SSV's.
 enum Mode : int {
     kSSV = 0,      // SSV (Alg. 7)
-    kMSV = 1,      // MSV (Alg. 2)
+    kMSV = 1,      // MSV (Alg. 2) with scB fixed
+    kMSVX = 2,     // MSV (Alg. 2) in exact mode over the windows kMSV listed
 };
 
-// Work-queue counter in the workspace.
-constexpr int kCtrMain = 0;      // next sequence of the range
+// Counters in the workspace.
+constexpr int kCtrMain = 0;      // next sequence of the range (kSSV, kMSV)
+constexpr int kCtrHot = 1;       // windows listed for exact rescoring
+constexpr int kCtrExact = 2;     // next window (kMSVX)
 
 // Sequence ends a wavefront collects before it leaves the row loop to
 // record scores and hand out sequences (see filter_kernel).
@@ -252,16 +261,7 @@ constexpr int kExitGroups = G == 1 ? 8 : G == 2 ? 4 : G == 4 ? 2 : 1;
 // Lanes with at most this many registers read each row's scores one row
 // ahead (a second set of Q registers).
 constexpr int kPipeQ = 17;
-constexpr int kPipeQMSV = 13;     // MSV also holds its exact-mode state
-
-// MSV groups of up to 4 lanes note the step in which a sequence's running
-// max passes base + tec, so a rescoring in exact mode starts there instead
-// of at the sequence's start.  Such plans serve short profiles, where the
-// J state opens often (scB starts closer to base); for the wider groups of
-// longer profiles the per-step check cost more than it saved (measured:
-// M = 64..192 2-18% faster, M = 400 and 768 1-1.5% slower).
-template <int G>
-constexpr bool kTrackHot = G <= 4;
+constexpr int kPipeQExact = 13;   // exact mode also holds the special states
 
 // Residue words (four residues each) per load and lane: 16 or 8 residues.
 template <int G>
@@ -270,26 +270,56 @@ constexpr int kWordsPerLoad = G <= 8 ? 4 : 2;
 // One filter launch.  Every lane group pulls sequences (longest first)
 // from the call's range and runs their rows in steps of 4K residues.
 //
-// MSV first runs a sequence with scB fixed at sat0(base - tjb - tbm).
-// Cells only grow with scB, and scB keeps that value until the running max
-// passes base + tec, so this result is exact when the running max stays at
-// or below base + tec (the J state never opens) or reaches the overflow
-// threshold.  Otherwise the group replays the sequence in exact mode (from
-// its first row, or from shortly before the point where the running max
-// first passed base + tec where that is known: groups of up to 4 lanes,
-// split sequences): after every row it checks (two instructions) whether any
-// cell passed the level at which scB would change or overflow occurs, and
-// only then runs Alg. 2's special-state update (group max, new scB, cells
-// lowered by the rise).  Waves without a group in exact mode skip the check.
+// kMSV runs a sequence with scB fixed at sat0(base - tjb - tbm).  Cells
+// relative to scB then follow the SSV-like recurrence u = max(0, u + dbias
+// - cost), and this result is exact when the running max stays at or below
+// base + tec (the J state never opens) or reaches the overflow threshold
+// (cells only grow with scB).  Otherwise the sequence is loud: the group
+// lists a window of its rows for kMSVX.  A step is loud if a cell in it
+// passed the level; rescoring in exact mode from `warm` (>= M - 1) rows
+// before the first loud step to the end of the last one gives the exact
+// score, because
+//  * before the first loud row scB never moved, so fresh cells started
+//    `warm` rows earlier are exact from that step on, and the rows skipped
+//    or warmed up stay at or below base + tec;
+//  * once scB has risen, relative cells follow the same recurrence and are
+//    only lowered at each rise, so they never exceed their fixed-scB
+//    values; after the last loud step no cell passes tjb + tbm + tec above
+//    scB, which is what a rise (or a first overflow) needs, so scJ, scB
+//    and the running max keep their values to the end.
+// kMSVX runs each window with Alg. 2's special states: after every row it
+// checks (two instructions) whether any cell passed the level at which scB
+// would change or overflow occurs, and only then runs the special-state
+// update (group max, new scB, cells lowered by the rise).
 template <int G, int Q, int MODE, int THREADS>
 __global__ void __launch_bounds__(THREADS)
 filter_kernel(KArgs a) {
-    constexpr bool MSV = MODE == kMSV;
+    constexpr bool MSV = MODE != kSSV;
+    constexpr bool FIRST = MODE == kMSV;
+    constexpr bool EXACT = MODE == kMSVX;
     extern __shared__ uint32_t lds[];
     using L = Lane<G, Q, MSV>;
     constexpr int W = L::W;
     constexpr int RS = L::RS;
     static_assert(RS % 4 == 0, "rows must stay 16-byte aligned");
+
+    const int ngroups = (int)(gridDim.x * (blockDim.x / G));
+    const int gid = (int)(blockIdx.x * (blockDim.x / G) + threadIdx.x / G);
+    // Records: the range's, with its split sequences (records [0, nsplit))
+    // replaced by their segments (nv = nsegs + nseq - nsplit records, the
+    // segments first); for kMSVX the windows kMSV listed.
+    const uint4 *recs = EXACT ? (const uint4 *)a.hot : (const uint4 *)a.seqs;
+    const uint4 *segs = (const uint4 *)a.segs;
+    const int nsegs = EXACT ? 0 : a.nsegs;
+    const int nsplit = EXACT ? 0 : a.nsplit;
+    int nv;
+    if constexpr (EXACT) {
+        nv = (int)a.counter[kCtrHot];          // final: written by the kMSV launch
+        // blocks without a window leave at once (see the start mapping below)
+        if ((int)(blockIdx.x * (blockDim.x / G)) >= nv) return;
+    } else {
+        nv = nsegs + a.nseq - nsplit;          // ranges are never empty
+    }
 
     // Stage the profile image (built by prep_kernel) into LDS.
     {
@@ -316,15 +346,15 @@ filter_kernel(KArgs a) {
     uint32_t seq_end = 0xffffffffu;   // offset just past the sequence's rows
     int tjbm = 0;
     int xb = 0;                  // MSV: scB (integer filter units)
-    int cm = -1;                 // MSV exact mode: exact running max of earlier scB epochs
-    int built = 0;               // MSV exact mode: running max scB was last computed from
-    uint32_t lvl = 0xffffffffu;  // MSV exact mode: check level (two u16 halves), all-ones = off
-    bool exact = false;          // MSV: group replays its sequence in exact mode
+    int cm = -1;                 // kMSVX: exact running max of earlier scB epochs
+    int built = 0;               // kMSVX: running max scB was last computed from
+    uint32_t lvl = 0xffffffffu;  // MSV: level (two u16 halves), all-ones = off
     bool ovf = false;
-    // MSV, scB fixed: offset of the first step after which this lane's
-    // running max passed base + tec (kNoHot: none yet)
-    constexpr uint32_t kNoHot = 0xffffffffu;
-    uint32_t hot = kNoHot;
+    // kMSV: running max over earlier steps (st.xE holds the current step's),
+    // and the offsets of this lane's first and last loud steps
+    constexpr uint32_t kNoStep = 0xffffffffu;
+    uint32_t xrun = 0u;
+    uint32_t first_loud = kNoStep, last_loud = 0u;
     bool active = false;
     bool need = false;           // group wants a sequence
     // Residues come in words of four, K words per load (16 residues for
@@ -356,17 +386,8 @@ filter_kernel(KArgs a) {
     // 2N records (shortest first from the end), positions from 3N (claimed
     // dynamically) the records in between, longest first.  No group thus
     // queues a long sequence behind its first one.  Ranges with fewer than
-    // 3N records use positions as record numbers.
-    //
-    // The records are the range's with its split sequences (records
-    // [0, nsplit)) replaced by their segments: nv = nsegs + nseq - nsplit
-    // records, the segments first.
-    const uint4 *recs = (const uint4 *)a.seqs;
-    const uint4 *segs = (const uint4 *)a.segs;
-    const int nsegs = a.nsegs;
-    const int nv = nsegs + a.nseq - a.nsplit;     // ranges are never empty
-    const int ngroups = (int)(gridDim.x * (blockDim.x / G));
-    const int gid = (int)(blockIdx.x * (blockDim.x / G) + threadIdx.x / G);
+    // 3N records use positions as record numbers (so a group whose number is
+    // at least the record count never gets one).
     const bool tail = nv >= 3 * ngroups;
     constexpr int kNone = 0x7fffffff;             // position past the range
     auto record_of = [&](int p) -> int {          // queue position -> record
@@ -377,30 +398,9 @@ filter_kernel(KArgs a) {
     };
     auto fetch = [&](int r, uint4 &h, uint4 &f) {
         r = r < nv ? r : nv - 1;
-        const uint4 *p = r < nsegs ? segs + 2 * r : recs + 2 * (r - nsegs + a.nsplit);
+        const uint4 *p = r < nsegs ? segs + 2 * r : recs + 2 * (r - nsegs + nsplit);
         h = p[0];
-        if constexpr (K > 1) f = p[1];
-    };
-    uint4 ra;                    // record A: off, rows | tjb << 24, id, first residues
-    uint4 ra16;                  // record A's first sixteen residues (K > 1)
-    int qa, qc;                  // records of A and of the claimed position (kNone: none)
-    uint32_t pend_b = 0;
-    int pend_first = -1;         // wave-uniform
-    auto start_record = [&](const uint4 &r, const uint4 &r16, bool valid) {
-        active = valid;
-        uint32_t rows = r.y & kRowsMask;
-        if constexpr (K > 1) rows = (rows + 4u * K - 1u) & ~(4u * K - 1u);
-        seq_off = valid ? r.x : a.pad_off;
-        seq_end = valid ? r.x + rows : a.pad_off;
-        id = r.z;
-        tjbm = (int)(r.y >> 24) + a.tbm;
-        if constexpr (K == 4) {
-            wv[0] = r16.x; wv[1] = r16.y; wv[2] = r16.z; wv[3] = r16.w;
-        } else if constexpr (K == 2) {
-            wv[0] = r16.x; wv[1] = r16.y;
-        } else {
-            wv[0] = r.w;
-        }
+        if constexpr (K > 1 && !EXACT) f = p[1];
     };
     // the residue words at offset o
     auto load_words = [&](uint32_t o, uint32_t (&d)[K]) {
@@ -414,11 +414,36 @@ filter_kernel(KArgs a) {
             d[0] = *(const uint32_t *)(a.res + o);
         }
     };
+    uint4 ra;                    // record A: off, rows | tjb << 24, id, first residues
+    uint4 ra16 = {0u, 0u, 0u, 0u};  // record A's first sixteen residues (K > 1)
+    int qa, qc;                  // records of A and of the claimed position (kNone: none)
+    uint32_t pend_b = 0;
+    int pend_first = -1;         // wave-uniform
+    auto start_record = [&](const uint4 &r, const uint4 &r16, bool valid) {
+        active = valid;
+        uint32_t rows = r.y & kRowsMask;
+        if constexpr (K > 1) rows = (rows + 4u * K - 1u) & ~(4u * K - 1u);
+        seq_off = valid ? r.x : a.pad_off;
+        seq_end = valid ? r.x + rows : a.pad_off;
+        id = r.z;
+        tjbm = (int)(r.y >> 24) + a.tbm;
+        if constexpr (EXACT) {
+            load_words(seq_off, wv);   // a window's record holds no residues
+        } else if constexpr (K == 4) {
+            wv[0] = r16.x; wv[1] = r16.y; wv[2] = r16.z; wv[3] = r16.w;
+        } else if constexpr (K == 2) {
+            wv[0] = r16.x; wv[1] = r16.y;
+        } else {
+            wv[0] = r.w;
+        }
+    };
 
     // MSV running max = max(cm, current epoch's max + scB); -1 while the
-    // current epoch never rose above scB.
+    // current epoch never rose above scB.  Called by whole wavefronts.
     auto epoch_max = [&]() -> int {
-        int m = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
+        uint32_t x = st.xE;
+        if constexpr (FIRST) x = hmax(x, xrun);
+        int m = bits_to_units(group_max<G>(lane_max_bits(x)));
         return m > 0 ? m + xb : -1;
     };
     // A cell above max(base + tec, built) moves scB (exact mode); one at or
@@ -447,19 +472,20 @@ filter_kernel(KArgs a) {
         cm = -1;
         built = 0;
         ovf = false;
-        hot = kNoHot;
-        set_level();
+        xrun = 0u;
+        first_loud = kNoStep;
+        last_loud = 0u;
+        if constexpr (MSV) set_level();
     };
 
     {
         int q0 = record_of(gid);
-        uint4 r0, r016;
+        uint4 r0, r016 = {0u, 0u, 0u, 0u};
         fetch(q0, r0, r016);
         qa = record_of(ngroups + gid);
         fetch(qa, ra, ra16);
         qc = record_of(2 * ngroups + gid);
         start_record(r0, r016, q0 != kNone);
-        exact = false;
         start_sequence();
     }
 
@@ -475,14 +501,15 @@ filter_kernel(KArgs a) {
             if (need) {
                 start_record(ra, ra16, qa != kNone);
                 qa = qc;
-                exact = false;
                 start_sequence();
             }
             fetch(qa, ra, ra16);
             // new claims for the groups that just switched
             unsigned long long m = __ballot(need && gstart);
             int first = __ffsll((long long)m) - 1;
-            if (lane == first) pend_b = atomicAdd(a.counter + kCtrMain, (uint32_t)__popcll(m));
+            if (lane == first)
+                pend_b = atomicAdd(a.counter + (EXACT ? kCtrExact : kCtrMain),
+                                   (uint32_t)__popcll(m));
             pend_first = first;
             // the group's rank: claiming groups below its first lane
             int rank = __popcll(m & ((1ull << (lane - j)) - 1ull));
@@ -490,7 +517,6 @@ filter_kernel(KArgs a) {
             need = false;
         }
         if (!__any(active)) break;
-        const bool wave_exact = MSV && __any(exact);
 
         // ---- rows, four residues at a time --------------------------------
         // A group that reaches its end parks: its offset moves to the
@@ -503,10 +529,10 @@ filter_kernel(KArgs a) {
         const int e_min = n_act < kExitGroups<G> ? n_act : kExitGroups<G>;
         const uint32_t step = active ? 4u * K : 0u;
         bool ended = false;
-        // Short rows (Q <= kPipeQ) are latency bound when a wavefront runs
-        // alone (the last, longest sequences of a launch): their scores are
-        // read one row ahead, into two alternating register sets.
-        constexpr bool PIPE = Q <= (MSV ? kPipeQMSV : kPipeQ);
+        // Short rows are latency bound when a wavefront runs alone (the
+        // last, longest sequences of a launch): their scores are read one
+        // row ahead, into two alternating register sets.
+        constexpr bool PIPE = Q <= (EXACT ? kPipeQExact : kPipeQ);
         uint32_t ca[PIPE ? Q : 1], cb[PIPE ? Q : 1];
         auto xrow = [&](int r) -> uint32_t { return (wv[r / 4] >> (8 * (r % 4))) & 0xffu; };
         if constexpr (PIPE) st.load_row(T[0], T[1], T[2], xrow(0), ca);
@@ -515,8 +541,8 @@ filter_kernel(KArgs a) {
             if constexpr (kExitGroups<G> > 1) offn = offn < seq_end ? offn : a.pad_off;
             uint32_t wn[K];
             load_words(offn, wn);                                    // next 4K residues
-            // one residue row; CHECK: MSV exact-mode check after it
-            auto one_row = [&](auto r_c, auto check_c) {
+            // one residue row, then (kMSVX) the exact-mode check
+            auto one_row = [&](auto r_c) {
                 constexpr int r = decltype(r_c)::value;
                 if constexpr (PIPE) {
                     uint32_t (&cur)[PIPE ? Q : 1] = (r & 1) ? cb : ca;
@@ -533,8 +559,8 @@ filter_kernel(KArgs a) {
                 } else {
                     st.row(T, xrow(r));
                 }
-                if constexpr (MSV && decltype(check_c)::value) {
-                    const bool hit = exact && above_level();
+                if constexpr (EXACT) {
+                    const bool hit = above_level();
                     if (__any(hit)) {
                         // Alg. 2 special states after this row, for every group
                         // whose running max passed its level (decided from the
@@ -542,7 +568,7 @@ filter_kernel(KArgs a) {
                         int e2 = epoch_max();
                         int m2 = cm > e2 ? cm : e2;
                         int lim = built > kBase + kTec ? built : kBase + kTec;
-                        if (exact && !ovf && (m2 > lim || m2 >= 255 - dbias)) {
+                        if (!ovf && (m2 > lim || m2 >= 255 - dbias)) {
                             if (m2 >= 255 - dbias) ovf = true;
                             int j2 = m2 - kTec > kBase ? m2 - kTec : kBase;
                             int xbn = j2 - tjbm;
@@ -559,21 +585,24 @@ filter_kernel(KArgs a) {
                     }
                 }
             };
-            auto all_rows = [&](auto check_c) {
-                [&]<int... R>(std::integer_sequence<int, R...>) {
-                    (one_row(std::integral_constant<int, R>{}, check_c), ...);
-                }(std::make_integer_sequence<int, 4 * K>{});
-            };
-            if (!wave_exact) all_rows(std::false_type{});
-            else all_rows(std::true_type{});
+            [&]<int... R>(std::integer_sequence<int, R...>) {
+                (one_row(std::integral_constant<int, R>{}), ...);
+            }(std::make_integer_sequence<int, 4 * K>{});
             // Consume the next words only here, so their load stays issued
             // before the rows and its latency hides behind them.
 #pragma unroll
             for (int k = 0; k < K; ++k) asm volatile("" : "+v"(wn[k]));
-            if constexpr (MSV && kTrackHot<G>) {
-                // scB fixed: remember the step in which the running max
-                // first passed base + tec (a rescoring starts shortly before)
-                if (!exact && hot == kNoHot && above_level()) hot = off;
+            if constexpr (FIRST) {
+                // the step's maximum joins the running max; note the step if
+                // a cell in it passed the level (parked groups, past their
+                // sequence, note nothing)
+                const bool loud = above_level() && off < seq_end;
+                xrun = hmax(xrun, st.xE);
+                st.xE = 0u;
+                if (loud) {
+                    first_loud = first_loud == kNoStep ? off : first_loud;
+                    last_loud = off;
+                }
             }
             off = offn;
             ended = active && off == (kExitGroups<G> > 1 ? a.pad_off : seq_end);
@@ -582,10 +611,41 @@ filter_kernel(KArgs a) {
         } while (__popcll(__ballot(ended && gstart)) < e_min);
 
         // ---- finished sequences: record scores (Alg. 2 end-residue branch) -----
-        int mx;
-        if constexpr (MSV) {
+        if constexpr (MODE == kSSV) {
+            int mx = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
+            // A split sequence's maximum is the maximum over its segments
+            // (every cell of the sequence lies in some segment's own rows,
+            // and a warm-up row's cells never exceed the true ones): SSV
+            // segments store theirs for combine_kernel.
+            if (ended && gstart) {
+                if (id & kSegBit) {
+                    a.segx[2 * (id & ~kSegBit)] = (uint32_t)mx;
+                } else {
+                    bool of = mx >= 255;
+                    a.score[id] = of ? (uint8_t)127 : (uint8_t)(int8_t)(mx - 128);
+                    a.flag[id] = of ? 1 : 0;
+                }
+            }
+            need = ended;
+        } else if constexpr (EXACT) {
             int em = epoch_max();
-            mx = cm > em ? cm : em;
+            int mx = cm > em ? cm : em;
+            if (ended && gstart) {
+                bool of = ovf || mx >= 255 - dbias;
+                int v = mx - kTec;
+                a.score[id] = of ? 255 : (uint8_t)(v < 0 ? 0 : v);
+                a.flag[id] = of ? 1 : 0;
+            }
+            need = ended;
+        } else {
+            // scB and tjb + tbm follow from the level (lim - scB, lim >= scB
+            // since scB <= base), so neither stays in a register over the rows
+            {
+                const int lim = kBase + kTec < 254 - dbias ? kBase + kTec : 254 - dbias;
+                xb = lim - bits_to_units((int)(lvl & 0xffffu));
+                tjbm = kBase - xb;
+            }
+            int mx = epoch_max();
             // never above scB: max(0, scB + best score of its residues)
             int bst = -(1 << 30);
             if (ended && mx < 0) {
@@ -599,111 +659,84 @@ filter_kernel(KArgs a) {
                 int v = xb + bst;
                 mx = v > 0 ? v : 0;
             }
-        } else {
-            mx = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
-        }
-        // A split sequence's maximum is the maximum over its segments
-        // (every cell of the sequence lies in some segment's own rows, and
-        // a warm-up row's cells never exceed the true ones).  SSV segments
-        // store theirs for combine_kernel.  MSV segments combine here, in
-        // their sequence's slot, so that the group ending the last segment
-        // can rescore the sequence at once if its J state may have opened;
-        // the slot also keeps the earliest offset at which a segment's
-        // running max passed base + tec (the step it happened in, for
-        // groups of up to 4 lanes, else the segment's start): scB cannot
-        // move before it, so the rescoring can start `warm` rows earlier
-        // with fresh cells (rows before that point stay at or below base +
-        // tec, and warm-up cells below the true ones).
-        if constexpr (MODE == kSSV) {
-            if (ended && gstart) {
-                if (id & kSegBit) {
-                    a.segx[2 * (id & ~kSegBit)] = (uint32_t)mx;
-                } else {
-                    bool of = mx >= 255;
-                    a.score[id] = of ? (uint8_t)127 : (uint8_t)(int8_t)(mx - 128);
-                    a.flag[id] = of ? 1 : 0;
-                }
-            }
-            need = ended;
-        } else {
+            // the group's first and last loud steps (unsigned min by a signed
+            // max of the flipped complement, unsigned max by a signed max of
+            // the flipped value); called by whole wavefronts
+            const uint32_t gfirst =
+                ~((uint32_t)group_max<G>((int)(~first_loud ^ 0x80000000u)) ^ 0x80000000u);
+            const uint32_t glast =
+                (uint32_t)group_max<G>((int)(last_loud ^ 0x80000000u)) ^ 0x80000000u;
             bool fin = ended;            // a whole sequence ends here
-            uint32_t sid = id;           // its original index (first lane)
-            int replay = -1;             // its record, if split
-            // the group's first step that passed base + tec (unsigned min
-            // over its lanes, by a signed max of the flipped complement);
-            // called by whole wavefronts
-            auto group_hot = [&]() -> uint32_t {
-                return ~((uint32_t)group_max<G>((int)(~hot ^ 0x80000000u)) ^ 0x80000000u);
-            };
-            uint32_t replay_off = kNoHot;  // the rescoring starts shortly before
+            uint32_t sid = id;           // its original index
+            uint32_t wfirst = gfirst, wlast = glast;
+            uint32_t sstart = seq_off, srt = 0u;   // its start and rows | tjb << 24
+            bool split = false;
+            // A split sequence's maximum and loud steps combine over its
+            // segments in its slot; the group that ends the last segment
+            // settles the sequence.
             if (__any(ended && (id & kSegBit))) {
                 const bool seg = ended && (id & kSegBit);
-                const uint32_t ghot = group_hot();
                 uint32_t *sl = nullptr;
                 if (seg) sl = a.slots + kSlotWords * a.segx[2 * (id & ~kSegBit) + 1];
                 int last = 0;
                 if (seg && gstart) {
                     atomicMax(sl + 1, (uint32_t)mx);
-                    // (without the per-step note, the segment's start)
-                    if (mx > kBase + kTec) atomicMin(sl + 4, ghot != kNoHot ? ghot : seq_off);
+                    if (gfirst != kNoStep) {
+                        atomicMin(sl + 4, gfirst);
+                        atomicMax(sl + 6, glast);
+                    }
                     __threadfence();
                     if (atomicSub(sl, 1u) == 1u) {
                         __threadfence();
                         last = 1;
                     }
                 }
-                // the group decides on a rescoring together: whether the
-                // first lane ended the last segment goes to every lane, which
-                // then reads the slot itself (at device scope, after the
-                // first lane's fence)
+                // whether the first lane ended the last segment goes to every
+                // lane of the group, which then reads the slot itself (at
+                // device scope, after the first lane's fence)
                 last = group_max<G>(last);
                 if (seg) {
                     fin = last != 0;
                     if (fin) {
                         mx = (int)__hip_atomic_load(sl + 1, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
+                        wfirst = __hip_atomic_load(sl + 4, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                        wlast = __hip_atomic_load(sl + 6, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
                         sid = sl[2];
-                        replay = (int)sl[3];
-                        replay_off = __hip_atomic_load(sl + 4, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
+                        split = true;
+                        const uint32_t *hr = (const uint32_t *)(recs + 2 * sl[3]);
+                        sstart = hr[0];
+                        srt = hr[1];
                     }
                 }
             }
-            bool of = ovf || mx >= 255 - dbias;
-            // the J state may have opened: replay in exact mode
-            bool redo = fin && !exact && !of && mx > kBase + kTec;
-            if (__any(redo && replay < 0)) {
-                const uint32_t ghot = group_hot();
-                if (replay < 0) replay_off = ghot;
-            }
-            if (fin && !redo && gstart) {
+            const bool of = mx >= 255 - dbias;
+            const bool loud = fin && !of && mx > kBase + kTec;
+            if (fin && !loud && gstart) {
                 int v = mx - kTec;
                 a.score[sid] = of ? 255 : (uint8_t)(v < 0 ? 0 : v);
                 a.flag[sid] = of ? 1 : 0;
             }
-            if (redo) {
-                // Rescore in exact mode from `warm` (>= M - 1) rows before
-                // the first step whose running max passed base + tec (over
-                // all segments of a split sequence).  Before that step scB
-                // never moved, so fresh cells from there are exact from the
-                // step on, and the rows skipped or warmed up stay at or
-                // below base + tec (warm-up cells see parts of their
-                // diagonals only).  A split sequence starts from its own
-                // record.
-                if (replay >= 0) {
-                    uint4 h, f;
-                    h = recs[2 * replay];
-                    f = recs[2 * replay + 1];
-                    start_record(h, f, true);
-                }
+            if (loud && gstart) {
+                // the window: `warm` rows before the first loud step (not
+                // before the sequence's start) to the end of the last one;
+                // never outside the sequence (a loud sequence always has a
+                // loud step, else the whole sequence)
                 const uint32_t w = (uint32_t)a.warm;
-                if (replay_off != kNoHot && replay_off >= seq_off + w)
-                    seq_off = (replay_off - w) & ~15u;
-                exact = true;
-                start_sequence();
-                load_words(seq_off, wv);
+                const uint32_t send =
+                    split ? sstart + (((srt & kRowsMask) + 4u * K - 1u) & ~(4u * K - 1u))
+                          : seq_end;
+                const bool known = wfirst != kNoStep && wfirst < send;
+                const uint32_t ws = known && wfirst >= sstart + w ? (wfirst - w) & ~15u : sstart;
+                uint32_t we = known ? wlast + 4u * K : send;
+                we = we < send ? we : send;
+                const uint32_t tjb = split ? srt >> 24 : (uint32_t)(tjbm - a.tbm);
+                const uint32_t h = atomicAdd(a.counter + kCtrHot, 1u);
+                *(uint4 *)(a.hot + h) = make_uint4(ws, (we - ws) | (tjb << 24), sid, 0u);
             }
-            need = ended && !redo;
+            need = ended;
         }
     }
 }
@@ -841,10 +874,19 @@ hipError_t launch_filter_kernel(const KArgs &a, int wpb, int blocks, hipStream_t
     return hipGetLastError();
 }
 
-// prep (LDS image, counter, MSV best scores), then the filter kernel.
+template <int G, int Q, int MODE>
+hipError_t launch_filter_mode(const KArgs &a, int wpb, int blocks, hipStream_t s) {
+    if constexpr (kMaxWaves<G> > 8) {
+        if (wpb > 8) return launch_filter_kernel<G, Q, MODE, 1024>(a, wpb, blocks, s);
+    }
+    return launch_filter_kernel<G, Q, MODE, 512>(a, wpb, blocks, s);
+}
+
+// prep (LDS image, counters, MSV best scores, split-sequence records), then
+// the filter kernel: SSV, or MSV with scB fixed followed by the exact-mode
+// windows (the second launch reads the window count the first one left).
 template <int G, int Q, bool MSV>
 hipError_t launch_filter(const KArgs &a, int wpb, int blocks, hipStream_t s) {
-    constexpr int MODE = MSV ? kMSV : kSSV;
     constexpr int n = kRows * Layout<G, Q>::RS;
     constexpr int nb = (n + 255) / 256;
     if (wpb < 1 || wpb > kMaxWaves<G>) return hipErrorInvalidValue;
@@ -853,13 +895,13 @@ hipError_t launch_filter(const KArgs &a, int wpb, int blocks, hipStream_t s) {
                        dim3(256), 0, s, a, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if constexpr (kMaxWaves<G> > 8) {
-        if (wpb > 8) e = launch_filter_kernel<G, Q, MODE, 1024>(a, wpb, blocks, s);
-        else e = launch_filter_kernel<G, Q, MODE, 512>(a, wpb, blocks, s);
-    } else {
-        e = launch_filter_kernel<G, Q, MODE, 512>(a, wpb, blocks, s);
+    if constexpr (MSV) {
+        e = launch_filter_mode<G, Q, kMSV>(a, wpb, blocks, s);
+        if (e != hipSuccess) return e;
+        return launch_filter_mode<G, Q, kMSVX>(a, wpb, blocks, s);
     }
-    if (e != hipSuccess || MSV || a.nsplit == 0) return e;
+    e = launch_filter_mode<G, Q, kSSV>(a, wpb, blocks, s);
+    if (e != hipSuccess || a.nsplit == 0) return e;
     hipLaunchKernelGGL(combine_kernel, dim3((a.nsplit + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }

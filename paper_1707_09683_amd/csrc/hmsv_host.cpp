@@ -221,6 +221,7 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
     a.segs = (SeqRec *)((char *)workspace + kWsSegOff);
     a.slots = (uint32_t *)((char *)workspace + kWsSlotOff);
     a.segx = (uint32_t *)((char *)workspace + kWsSegxOff);
+    a.hot = (SeqRec *)((char *)workspace + kWsHotOff);
     if (((uintptr_t)workspace & 255u) != 0) return HMSV_EINVAL;
 
     const int blocks = grid_blocks(e, plan, count);
@@ -476,8 +477,7 @@ size_t hmsv_plan_lds_bytes(int32_t G, int32_t Q) {
 }
 
 size_t hmsv_workspace_bytes(int64_t nseq) {
-    (void)nseq;   // fixed: split sequences and segments are capped per call
-    return kWsBytes;
+    return ws_bytes(nseq);
 }
 
 hmsv_status hmsv_msv_score(const hmsv_profile *prof, const hmsv_db *db, uint8_t *score,

@@ -37,10 +37,11 @@ constexpr uint32_t kSegBit = 0x80000000u;     // record is a segment (ids stay b
 // workspace, with two words per segment {SSV: its maximum, its split
 // sequence}, and each split sequence has a slot of kSlotWords words:
 // {MSV: segments left, MSV: combined maximum, original id, record,
-// MSV: earliest offset at which a segment's running max passed base + tec,
-// first segment, -, -}.  SSV segments store their maxima and a small kernel
-// combines them after the filter kernel; MSV combines in the filter
-// kernel, whose last segment decides on an exact rescoring.
+// MSV: offset of the earliest loud step, first segment, MSV: offset of the
+// latest loud step, -} (a loud step holds a cell above the level where scB
+// would rise).  SSV segments store their maxima and a small kernel combines
+// them after the filter kernel; MSV combines in the filter kernel, whose
+// last segment decides whether the sequence needs an exact rescoring.
 constexpr int kMaxSegs = 32768;       // segment records per call
 constexpr int kMaxSplit = 16384;      // split sequences per call
 constexpr int kMaxBins = 32;          // distinct segment counts per call
@@ -66,6 +67,8 @@ struct KArgs {
     SeqRec *segs;          // [kMaxSegs] segment records (workspace)
     uint32_t *slots;       // [kMaxSplit][kSlotWords] per split sequence (workspace)
     uint32_t *segx;        // [kMaxSegs][2] per segment (workspace)
+    SeqRec *hot;           // MSV: windows to rescore in exact mode, at most
+                           // one per sequence of the range (workspace)
     int32_t nsplit;
     int32_t nsegs;
     int32_t seg_rows;      // rows per segment (multiple of 16)
@@ -82,12 +85,16 @@ struct KArgs {
 
 // Workspace layout: queue counters (bytes 0..63), the MSV per-residue best
 // scores (bytes 64..147), the profile's LDS image from byte 256, then the
-// segment records and the split-sequence slots.
+// segment records, the split-sequence slots and, for MSV, one window
+// record per sequence of the database.
 constexpr size_t kWsCounterBytes = 256;
 constexpr size_t kWsSegOff = kWsCounterBytes + 160 * 1024;
 constexpr size_t kWsSlotOff = kWsSegOff + (size_t)kMaxSegs * sizeof(SeqRec);
 constexpr size_t kWsSegxOff = kWsSlotOff + (size_t)kMaxSplit * kSlotWords * 4;
-constexpr size_t kWsBytes = kWsSegxOff + (size_t)kMaxSegs * 8;
+constexpr size_t kWsHotOff = kWsSegxOff + (size_t)kMaxSegs * 8;
+inline size_t ws_bytes(int64_t nseq) {
+    return kWsHotOff + sizeof(SeqRec) * (size_t)(nseq > 1 ? nseq : 1);
+}
 
 typedef hipError_t (*LaunchFn)(const KArgs &, int waves_per_block, int blocks,
                                hipStream_t);

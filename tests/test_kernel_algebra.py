@@ -28,7 +28,16 @@ I7  a cell depends only on the M rows above it along its diagonal, so a
     before its first row with fresh cells: the maximum over the segments of
     their running maxima (SSV, and MSV with scB fixed) is the target's, since
     warm-up rows only see parts of their diagonals and so never exceed the
-    true cells.
+    true cells;
+I8  with scB fixed, relative cells follow one recurrence whatever scB is,
+    and an exact run only lowers them at each rise of scB, so they never
+    exceed their fixed-scB values.  scB rises (and a first overflow happens)
+    only in a row where a cell passes tjb + tbm + tec above scB, the level a
+    fixed-scB cell must pass for the running max to pass base + tec.  Call a
+    step loud if a fixed-scB cell in it passes that level: an exact run over
+    the rows from `warm` >= M - 1 before the first loud step to the end of
+    the last one, with fresh cells, gives the exact score (before the first
+    loud step scB never moved; after the last one nothing can change).
 """
 import numpy as np
 
@@ -480,3 +489,107 @@ def test_models_across_the_bias_range():
                 assert model_ssv(prof, x) == oracle.ssv_seq(prof, x), (dbias, M)
                 seen["ovf" if exp[1] else ("j" if exp[0] > q.BASE else "plain")] += 1
     assert min(seen.values()) > 10, seen
+
+
+def exact_run(prof, rows, tjbm):
+    """Alg. 2 special states after every row (cells relative to scB, I5),
+    from fresh cells: (exact running max or -1, overflow)."""
+    bias = prof["bias"]
+    s = bias - prof["cost"].astype(np.int64)
+    tec, base = q.tec(), q.BASE
+    xb = max(0, base - tjbm)
+    cm, run, flag = -1, 0, False
+    W = np.zeros(prof["M"], np.int64)
+    for r in rows:
+        W = np.maximum(0, np.concatenate(([0], W[:-1])) + s[r])
+        run = max(run, int(W.max()))
+        cc = max(cm, run + xb if run > 0 else -1)
+        if cc >= 255 - bias:
+            flag = True
+        xbn = max(0, max(base, cc - tec) - tjbm)
+        if xbn > xb:
+            W = np.maximum(0, W - (xbn - xb))
+            cm, run, xb = cc, 0, xbn
+    return max(cm, run + xb if run > 0 else -1), flag
+
+
+def model_msv_window(prof, x, step, warm, T=None, end_short=0, align=16):
+    """I8, as the kernels run MSV: pass 1 with scB fixed (segments of T rows
+    after `warm` warm-up rows if T is given, I7) notes the first and last
+    loud steps; the exact pass runs only the window from `warm` rows before
+    the first loud step (rounded down to 16) to the end of the last one
+    (`end_short` steps less, to show the bound is needed)."""
+    bias = prof["bias"]
+    s = bias - prof["cost"].astype(np.int64)
+    best = s.max(axis=1)
+    L = len(x)
+    rows = list(x) + [20] * ((-L) % step if L else step)
+    R = len(rows)
+    tjbm = q.tjb(L) + prof["tbm"]
+    tec, base = q.tec(), q.BASE
+    xb0 = max(0, base - tjbm)
+    level = min(base + tec, 254 - bias) - xb0
+    T = T or R
+    c, first, last = 0, None, None
+    for beg in range(0, R, T):
+        b0 = max(0, beg - warm)
+        W = np.zeros(prof["M"], np.int64)
+        run = 0
+        for i in range(b0, min(R, beg + T)):
+            W = np.maximum(0, np.concatenate(([0], W[:-1])) + s[rows[i]])
+            m = int(W.max())
+            run = max(run, m)
+            if m > level:                              # a loud row: its step is loud
+                st0 = b0 + ((i - b0) // step) * step
+                first = st0 if first is None else min(first, st0)
+                last = st0 if last is None else max(last, st0)
+        seg = rows[b0:min(R, beg + T)]
+        cs = run + xb0 if run > 0 else max(0, xb0 + int(max(best[r] for r in seg)))
+        c = max(c, cs)
+    if c >= 255 - bias:
+        return 255, 1
+    if c <= base + tec:
+        return max(0, c - tec), 0
+    ws = first - warm if first >= warm else 0
+    ws -= ws % align
+    we = last + step - end_short * step
+    cc, flag = exact_run(prof, rows[ws:we], tjbm)
+    if flag or cc >= 255 - bias:
+        return 255, 1
+    return max(0, cc - tec), 0
+
+
+def test_msv_windowed_rescore_matches_oracle():
+    """I8 on targets with several hits far apart (quiet stretches between
+    them), whole and split into segments, for both step sizes the kernels
+    use; a window one step short at its end, or (rows taken one at a time)
+    with one row less of warm-up, must fail somewhere."""
+    rng = np.random.default_rng(29)
+    regimes = {"ovf": 0, "j": 0, "plain": 0}
+    short_end = short_warm = 0
+    for trial in range(30):
+        M = int(rng.choice([1, 3, 16, 48]))
+        emis = synth.sample_emissions(rng, M)
+        prof = q.quantize(emis, synth.BG)
+        db = synth.random_db(rng, 8, 0, 500)
+        for _ in range(3):
+            synth.implant(rng, db.res, db.offsets, [emis], 0.5)
+        for sidx in range(db.n):
+            x = db.seq(sidx)
+            exp = oracle.msv_seq(prof, x)
+            w = max(0, M - 1)
+            for step in (8, 16):
+                assert model_msv_window(prof, x, step, w) == exp, (trial, sidx, step)
+                assert model_msv_window(prof, x, step, w + 16) == exp
+                for T in (64, 96):
+                    assert model_msv_window(prof, x, step, max(w, 16), T) == exp, \
+                        (trial, sidx, step, T)
+                short_end += model_msv_window(prof, x, step, w, end_short=1) != exp
+            if M > 1:
+                # rows one at a time, no rounding: M - 1 rows of warm-up suffice,
+                # M - 2 do not
+                assert model_msv_window(prof, x, 1, w, align=1) == exp
+                short_warm += model_msv_window(prof, x, 1, w - 1, align=1) != exp
+            regimes["ovf" if exp[1] else ("j" if exp[0] > q.BASE else "plain")] += 1
+    assert min(regimes.values()) > 3, regimes
+    assert short_end > 0 and short_warm > 0, (short_end, short_warm)
