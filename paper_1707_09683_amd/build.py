@@ -92,6 +92,9 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
     host_cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, "hmsv_host.cpp"),
                 "-o", host_obj]
     tasks.append((host_cmd, host_obj, _deps_hash(["host"])))
+    exact_obj = os.path.join(OBJ, "exact.o")
+    tasks.append(([HIPCC, *COMMON, "-c", os.path.join(CSRC, "exact.hip"), "-o", exact_obj],
+                  exact_obj, _deps_hash(["exact"])))
     for G, lo, hi in kernel_units():
         obj = os.path.join(OBJ, f"kernels_g{G}_q{lo}_{hi}.o")
         defs = [f"-DHMSV_G={G}", f"-DHMSV_QLO={lo}", f"-DHMSV_QHI={hi}"]

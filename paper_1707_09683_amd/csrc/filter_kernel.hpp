@@ -236,22 +236,23 @@ struct Lane {
     }
 };
 
-// Kernel modes.  MSV runs as two launches: kMSV scores every sequence with
-// scB fixed and settles all but the few whose running max passes base + tec
-// (where the J state may open); kMSVX then rescores those in exact mode,
-// each over a short window of its rows.  Keeping the exact-mode code out of
-// the kernel that does almost all of the work keeps its register count at
-// SSV's.
+// Kernel modes.  MSV runs as two launches: filter_kernel in mode kMSV
+// scores every sequence with scB fixed and settles all but the few whose
+// running max passes base + tec (where the J state may open); for those it
+// stores a short window of rows, and exact_kernel rescores each window in
+// exact mode.  Keeping the exact-mode
+// code out of the kernel that does almost all of the work keeps its
+// register count at SSV's.
 enum Mode : int {
     kSSV = 0,      // SSV (Alg. 7)
     kMSV = 1,      // MSV (Alg. 2) with scB fixed
-    kMSVX = 2,     // MSV (Alg. 2) in exact mode over the windows kMSV listed
 };
 
 // Counters in the workspace.
-constexpr int kCtrMain = 0;      // next sequence of the range (kSSV, kMSV)
-constexpr int kCtrHot = 1;       // windows listed for exact rescoring
-constexpr int kCtrExact = 2;     // next window (kMSVX)
+constexpr int kCtrMain = 0;      // next sequence of the range
+
+// Flag value that marks a sequence whose score the exact pass still owes.
+constexpr uint8_t kFlagPending = 2;
 
 // Sequence ends a wavefront collects before it leaves the row loop to
 // record scores and hand out sequences (see filter_kernel).
@@ -261,7 +262,6 @@ constexpr int kExitGroups = G == 1 ? 8 : G == 2 ? 4 : G == 4 ? 2 : 1;
 // Lanes with at most this many registers read each row's scores one row
 // ahead (a second set of Q registers).
 constexpr int kPipeQ = 17;
-constexpr int kPipeQExact = 13;   // exact mode also holds the special states
 
 // Residue words (four residues each) per load and lane: 16 or 8 residues.
 template <int G>
@@ -275,7 +275,8 @@ constexpr int kWordsPerLoad = G <= 8 ? 4 : 2;
 // - cost), and this result is exact when the running max stays at or below
 // base + tec (the J state never opens) or reaches the overflow threshold
 // (cells only grow with scB).  Otherwise the sequence is loud: the group
-// lists a window of its rows for kMSVX.  A step is loud if a cell in it
+// stores a window of its rows for exact_kernel (indexed by the sequence's
+// original index, flag set to kFlagPending).  A step is loud if a cell in it
 // passed the level; rescoring in exact mode from `warm` (>= M - 1) rows
 // before the first loud step to the end of the last one gives the exact
 // score, because
@@ -287,39 +288,15 @@ constexpr int kWordsPerLoad = G <= 8 ? 4 : 2;
 //    values; after the last loud step no cell passes tjb + tbm + tec above
 //    scB, which is what a rise (or a first overflow) needs, so scJ, scB
 //    and the running max keep their values to the end.
-// kMSVX runs each window with Alg. 2's special states: after every row it
-// checks (two instructions) whether any cell passed the level at which scB
-// would change or overflow occurs, and only then runs the special-state
-// update (group max, new scB, cells lowered by the rise).
 template <int G, int Q, int MODE, int THREADS>
 __global__ void __launch_bounds__(THREADS)
 filter_kernel(KArgs a) {
-    constexpr bool MSV = MODE != kSSV;
-    constexpr bool FIRST = MODE == kMSV;
-    constexpr bool EXACT = MODE == kMSVX;
+    constexpr bool MSV = MODE == kMSV;
     extern __shared__ uint32_t lds[];
     using L = Lane<G, Q, MSV>;
     constexpr int W = L::W;
     constexpr int RS = L::RS;
     static_assert(RS % 4 == 0, "rows must stay 16-byte aligned");
-
-    const int ngroups = (int)(gridDim.x * (blockDim.x / G));
-    const int gid = (int)(blockIdx.x * (blockDim.x / G) + threadIdx.x / G);
-    // Records: the range's, with its split sequences (records [0, nsplit))
-    // replaced by their segments (nv = nsegs + nseq - nsplit records, the
-    // segments first); for kMSVX the windows kMSV listed.
-    const uint4 *recs = EXACT ? (const uint4 *)a.hot : (const uint4 *)a.seqs;
-    const uint4 *segs = (const uint4 *)a.segs;
-    const int nsegs = EXACT ? 0 : a.nsegs;
-    const int nsplit = EXACT ? 0 : a.nsplit;
-    int nv;
-    if constexpr (EXACT) {
-        nv = (int)a.counter[kCtrHot];          // final: written by the kMSV launch
-        // blocks without a window leave at once (see the start mapping below)
-        if ((int)(blockIdx.x * (blockDim.x / G)) >= nv) return;
-    } else {
-        nv = nsegs + a.nseq - nsplit;          // ranges are never empty
-    }
 
     // Stage the profile image (built by prep_kernel) into LDS.
     {
@@ -339,6 +316,17 @@ filter_kernel(KArgs a) {
                             lds + Lay::OFF1 + Lay::lane_off(lane, 1)};
     const int dbias = a.dbias;
 
+    // Records: the range's, with its split sequences (records [0, nsplit))
+    // replaced by their segments (nv = nsegs + nseq - nsplit records, the
+    // segments first).
+    const uint4 *recs = (const uint4 *)a.seqs;
+    const uint4 *segs = (const uint4 *)a.segs;
+    const int nsegs = a.nsegs;
+    const int nsplit = a.nsplit;
+    const int nv = nsegs + a.nseq - nsplit;       // ranges are never empty
+    const int ngroups = (int)(gridDim.x * (blockDim.x / G));
+    const int gid = (int)(blockIdx.x * (blockDim.x / G) + threadIdx.x / G);
+
     L st;
     uint32_t off = a.pad_off;
     uint32_t id = 0;
@@ -346,11 +334,8 @@ filter_kernel(KArgs a) {
     uint32_t seq_end = 0xffffffffu;   // offset just past the sequence's rows
     int tjbm = 0;
     int xb = 0;                  // MSV: scB (integer filter units)
-    int cm = -1;                 // kMSVX: exact running max of earlier scB epochs
-    int built = 0;               // kMSVX: running max scB was last computed from
-    uint32_t lvl = 0xffffffffu;  // MSV: level (two u16 halves), all-ones = off
-    bool ovf = false;
-    // kMSV: running max over earlier steps (st.xE holds the current step's),
+    uint32_t lvl = 0xffffffffu;  // MSV: level (two u16 halves)
+    // MSV: running max over earlier steps (st.xE holds the current step's),
     // and the offsets of this lane's first and last loud steps
     constexpr uint32_t kNoStep = 0xffffffffu;
     uint32_t xrun = 0u;
@@ -400,7 +385,7 @@ filter_kernel(KArgs a) {
         r = r < nv ? r : nv - 1;
         const uint4 *p = r < nsegs ? segs + 2 * r : recs + 2 * (r - nsegs + nsplit);
         h = p[0];
-        if constexpr (K > 1 && !EXACT) f = p[1];
+        if constexpr (K > 1) f = p[1];
     };
     // the residue words at offset o
     auto load_words = [&](uint32_t o, uint32_t (&d)[K]) {
@@ -415,7 +400,7 @@ filter_kernel(KArgs a) {
         }
     };
     uint4 ra;                    // record A: off, rows | tjb << 24, id, first residues
-    uint4 ra16 = {0u, 0u, 0u, 0u};  // record A's first sixteen residues (K > 1)
+    uint4 ra16;                  // record A's first sixteen residues (K > 1)
     int qa, qc;                  // records of A and of the claimed position (kNone: none)
     uint32_t pend_b = 0;
     int pend_first = -1;         // wave-uniform
@@ -427,9 +412,7 @@ filter_kernel(KArgs a) {
         seq_end = valid ? r.x + rows : a.pad_off;
         id = r.z;
         tjbm = (int)(r.y >> 24) + a.tbm;
-        if constexpr (EXACT) {
-            load_words(seq_off, wv);   // a window's record holds no residues
-        } else if constexpr (K == 4) {
+        if constexpr (K == 4) {
             wv[0] = r16.x; wv[1] = r16.y; wv[2] = r16.z; wv[3] = r16.w;
         } else if constexpr (K == 2) {
             wv[0] = r16.x; wv[1] = r16.y;
@@ -438,44 +421,35 @@ filter_kernel(KArgs a) {
         }
     };
 
-    // MSV running max = max(cm, current epoch's max + scB); -1 while the
-    // current epoch never rose above scB.  Called by whole wavefronts.
-    auto epoch_max = [&]() -> int {
-        uint32_t x = st.xE;
-        if constexpr (FIRST) x = hmax(x, xrun);
-        int m = bits_to_units(group_max<G>(lane_max_bits(x)));
+    // MSV running max with scB fixed: max over the lane group of its cells'
+    // running max, plus scB; -1 while no cell rose above scB.  Called by
+    // whole wavefronts.
+    auto run_max = [&]() -> int {
+        int m = bits_to_units(group_max<G>(lane_max_bits(hmax(st.xE, xrun))));
         return m > 0 ? m + xb : -1;
     };
-    // A cell above max(base + tec, built) moves scB (exact mode); one at or
-    // above 255 - dbias overflows.  The level is the larger relative cell
-    // value that does neither, as an fp16 pattern in both halves.  With scB
-    // fixed (built = 0) it marks where the running max passes base + tec.
-    auto set_level = [&]() {
-        int lim = built > kBase + kTec ? built : kBase + kTec;
-        int top = 254 - dbias;
-        lim = lim < top ? lim : top;
-        int rel = lim - xb;
-        rel = rel < 0 ? 0 : rel;
-        lvl = ovf ? 0xffffffffu : units_splat(rel);
-    };
-    // any cell of this lane above the level?  (saturating u16 subtract)
+    // The level: the largest relative cell value at which the running max
+    // neither passes base + tec nor reaches 255 - dbias, as an fp16 pattern
+    // in both halves; and whether any cell of this lane's step passed it
+    // (saturating u16 subtract).
     auto above_level = [&]() -> bool {
         return (uint32_t)__builtin_bit_cast(
                    uint32_t, __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, st.xE),
                                                            __builtin_bit_cast(u16x2, lvl))) != 0u;
     };
+    const int lim0 = kBase + kTec < 254 - dbias ? kBase + kTec : 254 - dbias;
     auto start_sequence = [&]() {
         off = seq_off;
         xb = kBase - tjbm;
         xb = xb < 0 ? 0 : xb;
         st.reset();
-        cm = -1;
-        built = 0;
-        ovf = false;
         xrun = 0u;
         first_loud = kNoStep;
         last_loud = 0u;
-        if constexpr (MSV) set_level();
+        if constexpr (MSV) {
+            const int rel = lim0 - xb;
+            lvl = units_splat(rel < 0 ? 0 : rel);
+        }
     };
 
     {
@@ -507,9 +481,7 @@ filter_kernel(KArgs a) {
             // new claims for the groups that just switched
             unsigned long long m = __ballot(need && gstart);
             int first = __ffsll((long long)m) - 1;
-            if (lane == first)
-                pend_b = atomicAdd(a.counter + (EXACT ? kCtrExact : kCtrMain),
-                                   (uint32_t)__popcll(m));
+            if (lane == first) pend_b = atomicAdd(a.counter + kCtrMain, (uint32_t)__popcll(m));
             pend_first = first;
             // the group's rank: claiming groups below its first lane
             int rank = __popcll(m & ((1ull << (lane - j)) - 1ull));
@@ -532,7 +504,7 @@ filter_kernel(KArgs a) {
         // Short rows are latency bound when a wavefront runs alone (the
         // last, longest sequences of a launch): their scores are read one
         // row ahead, into two alternating register sets.
-        constexpr bool PIPE = Q <= (EXACT ? kPipeQExact : kPipeQ);
+        constexpr bool PIPE = Q <= kPipeQ;
         uint32_t ca[PIPE ? Q : 1], cb[PIPE ? Q : 1];
         auto xrow = [&](int r) -> uint32_t { return (wv[r / 4] >> (8 * (r % 4))) & 0xffu; };
         if constexpr (PIPE) st.load_row(T[0], T[1], T[2], xrow(0), ca);
@@ -541,7 +513,7 @@ filter_kernel(KArgs a) {
             if constexpr (kExitGroups<G> > 1) offn = offn < seq_end ? offn : a.pad_off;
             uint32_t wn[K];
             load_words(offn, wn);                                    // next 4K residues
-            // one residue row, then (kMSVX) the exact-mode check
+            // one residue row
             auto one_row = [&](auto r_c) {
                 constexpr int r = decltype(r_c)::value;
                 if constexpr (PIPE) {
@@ -559,31 +531,6 @@ filter_kernel(KArgs a) {
                 } else {
                     st.row(T, xrow(r));
                 }
-                if constexpr (EXACT) {
-                    const bool hit = above_level();
-                    if (__any(hit)) {
-                        // Alg. 2 special states after this row, for every group
-                        // whose running max passed its level (decided from the
-                        // group max, so all lanes of a group agree)
-                        int e2 = epoch_max();
-                        int m2 = cm > e2 ? cm : e2;
-                        int lim = built > kBase + kTec ? built : kBase + kTec;
-                        if (!ovf && (m2 > lim || m2 >= 255 - dbias)) {
-                            if (m2 >= 255 - dbias) ovf = true;
-                            int j2 = m2 - kTec > kBase ? m2 - kTec : kBase;
-                            int xbn = j2 - tjbm;
-                            xbn = xbn < 0 ? 0 : (xbn > 255 ? 255 : xbn);
-                            if (xbn > xb) {          // new scB epoch
-                                st.lower(xbn - xb);
-                                st.xE = 0u;
-                                cm = m2;
-                                xb = xbn;
-                            }
-                            built = m2;
-                            set_level();
-                        }
-                    }
-                }
             };
             [&]<int... R>(std::integer_sequence<int, R...>) {
                 (one_row(std::integral_constant<int, R>{}), ...);
@@ -592,7 +539,7 @@ filter_kernel(KArgs a) {
             // before the rows and its latency hides behind them.
 #pragma unroll
             for (int k = 0; k < K; ++k) asm volatile("" : "+v"(wn[k]));
-            if constexpr (FIRST) {
+            if constexpr (MSV) {
                 // the step's maximum joins the running max; note the step if
                 // a cell in it passed the level (parked groups, past their
                 // sequence, note nothing)
@@ -627,25 +574,12 @@ filter_kernel(KArgs a) {
                 }
             }
             need = ended;
-        } else if constexpr (EXACT) {
-            int em = epoch_max();
-            int mx = cm > em ? cm : em;
-            if (ended && gstart) {
-                bool of = ovf || mx >= 255 - dbias;
-                int v = mx - kTec;
-                a.score[id] = of ? 255 : (uint8_t)(v < 0 ? 0 : v);
-                a.flag[id] = of ? 1 : 0;
-            }
-            need = ended;
         } else {
             // scB and tjb + tbm follow from the level (lim - scB, lim >= scB
             // since scB <= base), so neither stays in a register over the rows
-            {
-                const int lim = kBase + kTec < 254 - dbias ? kBase + kTec : 254 - dbias;
-                xb = lim - bits_to_units((int)(lvl & 0xffffu));
-                tjbm = kBase - xb;
-            }
-            int mx = epoch_max();
+            xb = lim0 - bits_to_units((int)(lvl & 0xffffu));
+            tjbm = kBase - xb;
+            int mx = run_max();
             // never above scB: max(0, scB + best score of its residues)
             int bst = -(1 << 30);
             if (ended && mx < 0) {
@@ -733,8 +667,8 @@ filter_kernel(KArgs a) {
                 uint32_t we = known ? wlast + 4u * K : send;
                 we = we < send ? we : send;
                 const uint32_t tjb = split ? srt >> 24 : (uint32_t)(tjbm - a.tbm);
-                const uint32_t h = atomicAdd(a.counter + kCtrHot, 1u);
-                *(uint4 *)(a.hot + h) = make_uint4(ws, (we - ws) | (tjb << 24), sid, 0u);
+                a.win[sid] = make_uint4(ws, (we - ws) | (tjb << 24), sid, 0u);
+                a.flag[sid] = kFlagPending;
             }
             need = ended;
         }
@@ -792,25 +726,57 @@ static __global__ void __launch_bounds__(256) combine_kernel(KArgs a) {
     a.flag[id] = of ? 1 : 0;
 }
 
-// LDS image of the profile (see Layout): for table row x, register q and
-// lane j, the dword holds slots (q + 2jQ, q + (2j+1)Q) as two fp16 scores, in
-// every copy of q's chunk.  Threads 0..3 reset the work-queue counters.  For
-// MSV, kRows extra blocks compute best[x] = max_k (dbias - cost_k(x)).  The
-// last blocks build the records and slots of split sequences.
+// One dword of a profile's LDS image for a lane group of G lanes with Q
+// registers, laid out as D = lds_layout(G, Q) describes: for table row x,
+// register q and lane j, the dword holds slots (q + 2jQ, q + (2j+1)Q) as two
+// fp16 scores, in every copy of q's chunk.
+template <bool MSV>
+__device__ __forceinline__ uint32_t image_dword(const KArgs &a, const LdsLayout &D, int G, int Q,
+                                                int idx) {
+    const int x = idx / D.RS;
+    int rem = idx - x * D.RS;
+    int w, q0;
+    if (rem < D.OFF2) {
+        const int ch = rem / D.CW;
+        rem -= ch * D.CW;
+        w = 4;
+        q0 = ch * 4;
+    } else if (rem < D.OFF1) {
+        rem -= D.OFF2;
+        w = 2;
+        q0 = D.NF * 4;
+    } else {
+        rem -= D.OFF1;
+        w = 1;
+        q0 = D.NF * 4 + ((D.R & 2) ? 2 : 0);
+    }
+    rem %= G * w;                                  // same data in every copy
+    const int jj = rem / w;
+    const int qq = q0 + (rem - jj * w);
+    const int s0 = qq + Q * (2 * jj);
+    return qq >= Q ? 0u                            // padding of a partial chunk
+                   : slot_bits<MSV>(a, x, s0) | (slot_bits<MSV>(a, x, s0 + Q) << 16);
+}
+
+// Per call: the filter kernel's LDS image of the profile and, for MSV, the
+// exact pass's image (Layout<64, qx>); threads 0..3 reset the counters.
+// For MSV, kRows more blocks compute best[x] = max_k (dbias - cost_k(x)).
+// The last blocks build the records and slots of split sequences.
 template <int G, int Q, bool MSV>
-__global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks) {
-    using Lay = Layout<G, Q>;
-    constexpr int RS = Lay::RS;
-    const int seg_block0 = image_blocks + (MSV ? kRows : 0);
-    if ((int)blockIdx.x >= seg_block0) {
-        int t = ((int)blockIdx.x - seg_block0) * 256 + (int)threadIdx.x;
+__global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks, int ximage_blocks) {
+    constexpr LdsLayout D = lds_layout(G, Q);
+    const int best_block0 = image_blocks + ximage_blocks;
+    const int seg_block0 = best_block0 + (MSV ? kRows : 0);
+    const int b = (int)blockIdx.x;
+    if (b >= seg_block0) {
+        int t = (b - seg_block0) * 256 + (int)threadIdx.x;
         if (t < a.nsplit) build_segments(a, t);
         return;
     }
-    if ((int)blockIdx.x >= image_blocks) {
+    if (b >= best_block0) {
         // MSV: best[x] = max_k (dbias - cost_k(x)) for each table row x
         __shared__ int red[256];
-        int x = blockIdx.x - image_blocks;
+        int x = b - best_block0;
         int m = -(1 << 30);
         for (int k = threadIdx.x; k < a.M; k += blockDim.x) {
             int v = node_score<true>(a, x, k);
@@ -826,32 +792,194 @@ __global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks) {
         if (threadIdx.x == 0) a.best[x] = red[0];
         return;
     }
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx < 4) a.counter[idx] = 0u;
-    if (idx >= kRows * RS) return;
-    int x = idx / RS;
-    int rem = idx - x * RS;
-    int w, q0;
-    if (rem < Lay::OFF2) {
-        int ch = rem / Lay::CW;
-        rem -= ch * Lay::CW;
-        w = Lay::W;
-        q0 = ch * Lay::W;
-    } else if (rem < Lay::OFF1) {
-        rem -= Lay::OFF2;
-        w = 2;
-        q0 = Lay::Q2;
-    } else {
-        rem -= Lay::OFF1;
-        w = 1;
-        q0 = Lay::Q1;
+    if (b >= image_blocks) {
+        // MSV: the exact pass's image
+        const LdsLayout X = lds_layout(kExactG, a.qx);
+        const int idx = (b - image_blocks) * 256 + (int)threadIdx.x;
+        if (idx < kRows * X.RS) a.ximage[idx] = image_dword<true>(a, X, kExactG, a.qx, idx);
+        return;
     }
-    rem %= G * w;                                  // same data in every copy
-    int jj = rem / w;
-    int qq = q0 + (rem - jj * w);
-    int s0 = qq + Q * (2 * jj);
-    a.image[idx] = qq >= Q ? 0u                    // padding of a partial chunk
-                           : slot_bits<MSV>(a, x, s0) | (slot_bits<MSV>(a, x, s0 + Q) << 16);
+    const int idx = b * 256 + (int)threadIdx.x;
+    if (idx < 4) a.counter[idx] = 0u;
+    if (idx < kRows * D.RS) a.image[idx] = image_dword<MSV>(a, D, G, Q, idx);
+}
+
+// MSV exact pass over the windows the filter kernel stored (Alg. 2 with
+// its special states after every row).  Each wavefront owns a contiguous
+// chunk of the call's records and rescores those whose flag the filter
+// kernel left at kFlagPending, one window at a time, as a single 64-lane
+// group holding QX registers of two cells per lane: the rows of a window
+// depend on each other, and with few registers per lane a row is a few
+// instructions.  A window {start offset, rows | tjb << 24, original id}
+// starts with fresh cells and scB at sat0(base - tjb - tbm).
+//
+// Rows run in steps of 16 with scB fixed; since scE is a running maximum,
+// one saturating u16 subtract of it against the level at the end of a step
+// tells whether any cell in the step passed the value at which scB would
+// change or the score overflows (invariant I4 of the kernel algebra).  Only
+// then is the step replayed from a copy of its starting cells with that
+// check after every row, and the special-state update (group max, new scJ
+// and scB, cells lowered by the rise of scB: u becomes max(u - d, 0)) run
+// where it fires.
+template <int QX, int THREADS>
+__global__ void __launch_bounds__(THREADS) exact_kernel(KArgs a) {
+    constexpr int G = kExactG;
+    using L = Lane<G, QX, true>;
+    using Lay = typename L::Lay;
+    constexpr int RS = Lay::RS;
+    const int lane = threadIdx.x & 63;
+    const uint32_t waves = blockDim.x / 64;
+    const uint32_t nw = gridDim.x * waves;
+    const uint32_t w = blockIdx.x * waves + threadIdx.x / 64;
+    const uint32_t count = (uint32_t)a.nseq;
+    const uint32_t chunk = (count + nw - 1) / nw;
+    const uint32_t lo = w * chunk < count ? w * chunk : count;
+    const uint32_t hi = lo + chunk < count ? lo + chunk : count;
+    auto pending = [&](uint32_t t, uint32_t &id) -> bool {
+        id = t < hi ? a.seqs[t].id : 0u;
+        return t < hi && a.flag[id] == kFlagPending;
+    };
+    bool mine = false;
+    for (uint32_t t0 = lo; t0 < hi; t0 += 64) {
+        uint32_t id;
+        mine = mine || __any(pending(t0 + lane, id));
+    }
+    if (!__syncthreads_or(mine)) return;          // no window in this block
+    extern __shared__ uint32_t lds[];
+    {
+        const uint4 *src = (const uint4 *)a.ximage;
+        uint4 *dst = (uint4 *)lds;
+        constexpr int n16 = kRows * RS / 4;
+        for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+    if (!mine) return;
+    const uint32_t *T[3] = {lds + Lay::lane_off(lane, 4),
+                            lds + Lay::OFF2 + Lay::lane_off(lane, 2),
+                            lds + Lay::OFF1 + Lay::lane_off(lane, 1)};
+    const int dbias = a.dbias;
+    const int top = 254 - dbias;
+    L st;
+    for (uint32_t t0 = lo; t0 < hi; t0 += 64) {
+        uint32_t myid;
+        unsigned long long todo = __ballot(pending(t0 + lane, myid));
+        while (todo) {
+            const int k = __ffsll((long long)todo) - 1;
+            todo &= todo - 1ull;
+            const uint32_t sid = (uint32_t)__builtin_amdgcn_readlane((int)myid, k);
+            const uint4 r = a.win[sid];
+            const uint32_t ws = r.x, rows = r.y & kRowsMask;
+            const int tjbm = (int)(r.y >> 24) + a.tbm;
+            int xb = kBase - tjbm;
+            xb = xb < 0 ? 0 : xb;
+            int cm = -1;              // exact running max of earlier scB epochs
+            int built = 0;            // running max scB was last computed from
+            bool ovf = false;
+            uint32_t lvl = 0u;
+            // the level: the largest relative cell value at which the running
+            // max neither passes max(base + tec, built) nor reaches 255 - dbias
+            auto set_level = [&]() {
+                int lim = built > kBase + kTec ? built : kBase + kTec;
+                lim = lim < top ? lim : top;
+                int rel = lim - xb;
+                rel = rel < 0 ? 0 : rel;
+                lvl = ovf ? 0xffffffffu : units_splat(rel);
+            };
+            auto above_level = [&]() -> bool {
+                return (uint32_t)__builtin_bit_cast(
+                           uint32_t, __builtin_elementwise_sub_sat(
+                                         __builtin_bit_cast(u16x2, st.xE),
+                                         __builtin_bit_cast(u16x2, lvl))) != 0u;
+            };
+            // running max = max(cm, current epoch's max + scB); -1 while the
+            // current epoch never rose above scB
+            auto epoch_max = [&]() -> int {
+                int m = bits_to_units(group_max<G>(lane_max_bits(st.xE)));
+                return m > 0 ? m + xb : -1;
+            };
+            set_level();
+            st.reset();
+            // The window's residues come 1024 at a time, 16 per lane (windows
+            // start 16-byte aligned and hold a multiple of 8 rows, so the last
+            // lane's load stays in the sequence's padding); each step takes
+            // its 16 from one lane into scalar registers.  Scores are read
+            // one row ahead.
+            uint4 blk = make_uint4(0u, 0u, 0u, 0u);
+            uint32_t ca[QX], cb[QX];
+            for (uint32_t s = 0; s < rows; s += 16) {
+                if ((s & 1023u) == 0u) {
+                    const uint32_t o = s + 16u * (uint32_t)lane;
+                    blk = o < rows ? *(const uint4 *)(a.res + ws + o) : make_uint4(0u, 0u, 0u, 0u);
+                }
+                const int src = (int)((s & 1023u) >> 4);
+                uint4 wv;
+                wv.x = (uint32_t)__builtin_amdgcn_readlane((int)blk.x, src);
+                wv.y = (uint32_t)__builtin_amdgcn_readlane((int)blk.y, src);
+                wv.z = (uint32_t)__builtin_amdgcn_readlane((int)blk.z, src);
+                wv.w = (uint32_t)__builtin_amdgcn_readlane((int)blk.w, src);
+                auto xrow = [&](int k2) -> uint32_t {
+                    const uint32_t word = k2 < 4 ? wv.x : k2 < 8 ? wv.y : k2 < 12 ? wv.z : wv.w;
+                    return (word >> (8 * (k2 % 4))) & 0xffu;
+                };
+                // the step's rows; CHECK: the special states after each row
+                auto step = [&](auto check_c) {
+                    st.load_row(T[0], T[1], T[2], xrow(0), ca);
+                    auto one_row = [&](auto k_c) {
+                        constexpr int k2 = decltype(k_c)::value;
+                        uint32_t (&cur)[QX] = (k2 & 1) ? cb : ca;
+                        uint32_t (&nxt)[QX] = (k2 & 1) ? ca : cb;
+                        if (s + k2 >= rows) return;          // rows are a multiple of 8
+                        if constexpr (k2 + 1 < 16) st.load_row(T[0], T[1], T[2], xrow(k2 + 1), nxt);
+                        st.update(cur);
+                        if constexpr (decltype(check_c)::value) {
+                            if (__any(above_level())) {
+                                int e2 = epoch_max();
+                                int m2 = cm > e2 ? cm : e2;
+                                int lim = built > kBase + kTec ? built : kBase + kTec;
+                                if (!ovf && (m2 > lim || m2 >= 255 - dbias)) {
+                                    if (m2 >= 255 - dbias) ovf = true;
+                                    int j2 = m2 - kTec > kBase ? m2 - kTec : kBase;
+                                    int xbn = j2 - tjbm;
+                                    xbn = xbn < 0 ? 0 : (xbn > 255 ? 255 : xbn);
+                                    if (xbn > xb) {          // new scB epoch
+                                        st.lower(xbn - xb);
+                                        st.xE = 0u;
+                                        cm = m2;
+                                        xb = xbn;
+                                    }
+                                    built = m2;
+                                    set_level();
+                                }
+                            }
+                        }
+                    };
+                    [&]<int... R>(std::integer_sequence<int, R...>) {
+                        (one_row(std::integral_constant<int, R>{}), ...);
+                    }(std::make_integer_sequence<int, 16>{});
+                };
+                uint32_t save[QX];
+#pragma unroll
+                for (int q = 0; q < QX; ++q) save[q] = st.R[q];
+                const uint32_t save_xe = st.xE;
+                step(std::false_type{});
+                if (__any(above_level())) {
+                    // replay the step from its starting cells, row by row
+#pragma unroll
+                    for (int q = 0; q < QX; ++q) st.R[q] = save[q];
+                    st.xE = save_xe;
+                    step(std::true_type{});
+                }
+            }
+            int em = epoch_max();
+            int mx = cm > em ? cm : em;
+            if (lane == 0) {
+                const bool of = ovf || mx >= 255 - dbias;
+                const int v = mx - kTec;
+                a.score[sid] = of ? 255 : (uint8_t)(v < 0 ? 0 : v);
+                a.flag[sid] = of ? 1 : 0;
+            }
+        }
+    }
 }
 
 // Block sizes: up to 8 wavefronts, or up to 16 for groups of 32 and 64 lanes
@@ -882,24 +1010,21 @@ hipError_t launch_filter_mode(const KArgs &a, int wpb, int blocks, hipStream_t s
     return launch_filter_kernel<G, Q, MODE, 512>(a, wpb, blocks, s);
 }
 
-// prep (LDS image, counters, MSV best scores, split-sequence records), then
-// the filter kernel: SSV, or MSV with scB fixed followed by the exact-mode
-// windows (the second launch reads the window count the first one left).
+// prep (LDS images, counters, MSV best scores, split-sequence records),
+// then the filter kernel: SSV (and the combination of split sequences), or
+// MSV with scB fixed (the host launches the exact pass next).
 template <int G, int Q, bool MSV>
 hipError_t launch_filter(const KArgs &a, int wpb, int blocks, hipStream_t s) {
     constexpr int n = kRows * Layout<G, Q>::RS;
     constexpr int nb = (n + 255) / 256;
     if (wpb < 1 || wpb > kMaxWaves<G>) return hipErrorInvalidValue;
+    const int xb = MSV ? (kRows * lds_layout(kExactG, a.qx).RS + 255) / 256 : 0;
     const int seg_blocks = (a.nsplit + 255) / 256;
-    hipLaunchKernelGGL((prep_kernel<G, Q, MSV>), dim3(nb + (MSV ? kRows : 0) + seg_blocks),
-                       dim3(256), 0, s, a, nb);
+    hipLaunchKernelGGL((prep_kernel<G, Q, MSV>), dim3(nb + xb + (MSV ? kRows : 0) + seg_blocks),
+                       dim3(256), 0, s, a, nb, xb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if constexpr (MSV) {
-        e = launch_filter_mode<G, Q, kMSV>(a, wpb, blocks, s);
-        if (e != hipSuccess) return e;
-        return launch_filter_mode<G, Q, kMSVX>(a, wpb, blocks, s);
-    }
+    if constexpr (MSV) return launch_filter_mode<G, Q, kMSV>(a, wpb, blocks, s);
     e = launch_filter_mode<G, Q, kSSV>(a, wpb, blocks, s);
     if (e != hipSuccess || a.nsplit == 0) return e;
     hipLaunchKernelGGL(combine_kernel, dim3((a.nsplit + 255) / 256), dim3(256), 0, s, a);
@@ -927,6 +1052,25 @@ int occupancy_filter(int wpb) {
         if (wpb > 8) return occupancy_kernel<G, Q, MODE, 1024>(wpb);
     }
     return occupancy_kernel<G, Q, MODE, 512>(wpb);
+}
+
+// The exact pass: blocks of four wavefronts, as many as fit on the device
+// at once (blocks without a window leave after their scan).
+constexpr int kExactThreads = 256;
+
+template <int QX>
+hipError_t launch_exact(const KArgs &a, int cus, hipStream_t s) {
+    const size_t lds = lds_bytes(kExactG, QX);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)exact_kernel<QX, kExactThreads>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = (int)((size_t)kLdsBytes / lds);
+    per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
+    hipLaunchKernelGGL((exact_kernel<QX, kExactThreads>), dim3(cus * per_cu),
+                       dim3(kExactThreads), lds, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace hmsv

@@ -49,6 +49,7 @@ int32_t third_bit_cost(double p) { return (int32_t)(-rhaz(3.0 * std::log2(p))); 
 
 struct Registry {
     std::vector<KernelEntry> entries;
+    ExactLaunchFn exact[kMaxExactQ + 1] = {};
     const KernelEntry *find(int is_msv, int G, int Q) const {
         for (const auto &e : entries)
             if (e.is_msv == is_msv && e.G == G && e.Q == Q) return &e;
@@ -78,6 +79,26 @@ constexpr int kOccCap = 4096;
 std::mutex g_occ_mu;
 OccEntry g_occ[kOccCap];
 int g_nocc = 0;
+
+// Compute units of the current device (fixed table, no allocation).
+int device_cus() {
+    static std::mutex mu;
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+    if (dev < 64) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (cus[dev] > 0) return cus[dev];
+    }
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (dev < 64) {
+        std::lock_guard<std::mutex> lk(mu);
+        cus[dev] = n;
+    }
+    return n;
+}
 
 int resident_blocks(const KernelEntry *e, int wpb) {
     int dev = 0;
@@ -221,14 +242,26 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
     a.segs = (SeqRec *)((char *)workspace + kWsSegOff);
     a.slots = (uint32_t *)((char *)workspace + kWsSlotOff);
     a.segx = (uint32_t *)((char *)workspace + kWsSegxOff);
-    a.hot = (SeqRec *)((char *)workspace + kWsHotOff);
+    a.ximage = (uint32_t *)((char *)workspace + kWsXImageOff);
+    a.win = (uint4 *)((char *)workspace + kWsWinOff);
+    a.qx = exact_q(prof->M);
     if (((uintptr_t)workspace & 255u) != 0) return HMSV_EINVAL;
 
     const int blocks = grid_blocks(e, plan, count);
     if (blocks <= 0) return HMSV_EDEVICE;
     plan_split(db, first, count, (int64_t)blocks * plan.waves_per_block * (64 / plan.G),
                prof->M, a);
+    // MSV: a second kernel rescores the windows the first one stored
+    ExactLaunchFn xf = nullptr;
+    int cus = 0;
+    if (is_msv) {
+        xf = a.qx >= 1 && a.qx <= kMaxExactQ ? registry().exact[a.qx] : nullptr;
+        if (!xf) return HMSV_ENOKERNEL;
+        cus = device_cus();
+        if (cus <= 0) return HMSV_EDEVICE;
+    }
     if (e->launch(a, plan.waves_per_block, blocks, stream) != hipSuccess) return HMSV_EDEVICE;
+    if (xf && xf(a, cus, stream) != hipSuccess) return HMSV_EDEVICE;
     return HMSV_OK;
 }
 
@@ -238,6 +271,11 @@ namespace hmsv {
 int register_kernels(const KernelEntry *entries, int n) {
     registry().entries.insert(registry().entries.end(), entries, entries + n);
     return n;
+}
+
+int register_exact(int qx, ExactLaunchFn fn) {
+    if (qx >= 1 && qx <= kMaxExactQ) registry().exact[qx] = fn;
+    return qx;
 }
 
 }  // namespace hmsv

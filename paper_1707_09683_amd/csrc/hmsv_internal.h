@@ -67,8 +67,11 @@ struct KArgs {
     SeqRec *segs;          // [kMaxSegs] segment records (workspace)
     uint32_t *slots;       // [kMaxSplit][kSlotWords] per split sequence (workspace)
     uint32_t *segx;        // [kMaxSegs][2] per segment (workspace)
-    SeqRec *hot;           // MSV: windows to rescore in exact mode, at most
-                           // one per sequence of the range (workspace)
+    // MSV exact pass: windows {start, rows | tjb << 24, original id, -} of
+    // the sequences it rescores, by original index
+    uint4 *win;            // [database nseq] (workspace)
+    uint32_t *ximage;      // its LDS image of the profile (workspace)
+    int32_t qx;            // its registers per lane (64-lane groups)
     int32_t nsplit;
     int32_t nsegs;
     int32_t seg_rows;      // rows per segment (multiple of 16)
@@ -85,19 +88,20 @@ struct KArgs {
 
 // Workspace layout: queue counters (bytes 0..63), the MSV per-residue best
 // scores (bytes 64..147), the profile's LDS image from byte 256, then the
-// segment records, the split-sequence slots and, for MSV, one window
-// record per sequence of the database.
+// segment records, the split-sequence slots, the MSV exact pass's LDS
+// image and a 16-byte window record per sequence of the database (by
+// original index).
 constexpr size_t kWsCounterBytes = 256;
 constexpr size_t kWsSegOff = kWsCounterBytes + 160 * 1024;
 constexpr size_t kWsSlotOff = kWsSegOff + (size_t)kMaxSegs * sizeof(SeqRec);
 constexpr size_t kWsSegxOff = kWsSlotOff + (size_t)kMaxSplit * kSlotWords * 4;
-constexpr size_t kWsHotOff = kWsSegxOff + (size_t)kMaxSegs * 8;
-inline size_t ws_bytes(int64_t nseq) {
-    return kWsHotOff + sizeof(SeqRec) * (size_t)(nseq > 1 ? nseq : 1);
-}
+constexpr size_t kWsXImageOff = kWsSegxOff + (size_t)kMaxSegs * 8;
+constexpr size_t kWsWinOff = kWsXImageOff + 160 * 1024;
+inline size_t ws_bytes(int64_t nseq) { return kWsWinOff + 16 * (size_t)(nseq > 1 ? nseq : 1); }
 
 typedef hipError_t (*LaunchFn)(const KArgs &, int waves_per_block, int blocks,
                                hipStream_t);
+typedef hipError_t (*ExactLaunchFn)(const KArgs &, int cus, hipStream_t);
 typedef int (*OccupancyFn)(int waves_per_block);
 
 struct KernelEntry {
@@ -152,6 +156,14 @@ inline int64_t plan_nodes(int G, int Q) { return (int64_t)2 * G * Q - 1; }
 
 // Each kernel translation unit registers its instantiations at load time.
 int register_kernels(const KernelEntry *entries, int n);
+
+// The MSV exact pass runs one window per wavefront as a single 64-lane
+// group with the fewest registers that hold the profile: one kernel per
+// register count qx = 1..kMaxExactQ.
+constexpr int kExactG = 64;
+constexpr int kMaxExactQ = 30;
+inline int exact_q(int M) { return (M + 1 + 2 * kExactG - 1) / (2 * kExactG); }
+int register_exact(int qx, ExactLaunchFn fn);
 
 
 }  // namespace hmsv

@@ -228,3 +228,34 @@ def test_repeated_calls_share_workspace(hm, cfg0):
     for s, f in outs[1:]:
         assert torch.equal(s, outs[0][0]) and torch.equal(f, outs[0][1])
     gdb.close()
+
+
+@pytest.mark.parametrize("M", [30, 48, 130, 700])
+def test_msv_windows_at_sequence_edges(hm, M):
+    """Rescoring windows that start at a sequence's first row (a hit within
+    M rows of the start), end at its last row, or span two hits far apart,
+    for every group width of the first pass; the exact pass takes 64-lane
+    groups of 1, 1, 2 and 6 registers at these lengths."""
+    rng = np.random.default_rng(1300 + M)
+    emis = synth.sample_emissions(rng, M)
+    db = synth.random_db(rng, 1200, 40, 2500)
+    p = emis / emis.sum(axis=1, keepdims=True)
+    for i in range(db.n):
+        a, b = int(db.offsets[i]), int(db.offsets[i + 1])
+        ln = int(min(10, M, b - a))
+        k0 = int(rng.integers(0, M - ln + 1))
+        where = [a, b - ln, a + (b - a - ln) // 2][i % 3:i % 3 + 1]
+        if i % 4 == 3:
+            where = [a + 3, b - ln - 2]                     # two hits far apart
+        for at in where:
+            for t in range(ln):
+                db.res[at + t] = rng.choice(20, p=p[k0 + t])
+    exp = _oracle("msv", emis, db)
+    assert int(((exp[0] > 190) & (exp[1] == 0)).sum()) > 100
+    for G in (1, 2, 4, 8, 16, 32, 64):
+        Q = -(-(M + 1) // (2 * G))
+        if Q > 32 or hm.plan_lds_bytes(G, Q) > 160 * 1024:
+            continue
+        print(f"case msv windows M={M} G={G} Q={Q}", flush=True)
+        _assert_same(_gpu(hm, "msv", emis, db, hm.make_plan(G, Q, 4, 0)), exp,
+                     what=f"M={M} G={G}")
