@@ -805,9 +805,11 @@ __global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks, in
 }
 
 // MSV exact pass over the windows the filter kernel stored (Alg. 2 with
-// its special states after every row).  Each wavefront owns a contiguous
-// chunk of the call's records and rescores those whose flag the filter
-// kernel left at kFlagPending, one window at a time, as a single 64-lane
+// its special states after every row).  Wavefront w of nw owns records
+// w, w + nw, w + 2 nw, ... of the call (interleaved: records run longest
+// first, and long sequences have more and longer windows) and rescores
+// those whose flag the filter kernel left at kFlagPending, one window at a
+// time, as a single 64-lane
 // group holding QX registers of two cells per lane: the rows of a window
 // depend on each other, and with few registers per lane a row is a few
 // instructions.  A window {start offset, rows | tjb << 24, original id}
@@ -821,6 +823,8 @@ __global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks, in
 // check after every row, and the special-state update (group max, new scJ
 // and scB, cells lowered by the rise of scB: u becomes max(u - d, 0)) run
 // where it fires.
+constexpr int kExactAhead = 3;
+
 template <int QX, int THREADS>
 __global__ void __launch_bounds__(THREADS) exact_kernel(KArgs a) {
     constexpr int G = kExactG;
@@ -832,17 +836,17 @@ __global__ void __launch_bounds__(THREADS) exact_kernel(KArgs a) {
     const uint32_t nw = gridDim.x * waves;
     const uint32_t w = blockIdx.x * waves + threadIdx.x / 64;
     const uint32_t count = (uint32_t)a.nseq;
-    const uint32_t chunk = (count + nw - 1) / nw;
-    const uint32_t lo = w * chunk < count ? w * chunk : count;
-    const uint32_t hi = lo + chunk < count ? lo + chunk : count;
-    auto pending = [&](uint32_t t, uint32_t &id) -> bool {
-        id = t < hi ? a.seqs[t].id : 0u;
-        return t < hi && a.flag[id] == kFlagPending;
+    // this wavefront's records: w + (b * 64 + lane) * nw for batches b
+    const uint32_t nb = (count + 64u * nw - 1u) / (64u * nw);
+    auto pending = [&](uint32_t b, uint32_t &id) -> bool {
+        const uint32_t t = w + (b * 64u + (uint32_t)lane) * nw;
+        id = t < count ? a.seqs[t].id : 0u;
+        return t < count && a.flag[id] == kFlagPending;
     };
     bool mine = false;
-    for (uint32_t t0 = lo; t0 < hi; t0 += 64) {
+    for (uint32_t b = 0; b < nb; ++b) {
         uint32_t id;
-        mine = mine || __any(pending(t0 + lane, id));
+        mine = mine || __any(pending(b, id));
     }
     if (!__syncthreads_or(mine)) return;          // no window in this block
     extern __shared__ uint32_t lds[];
@@ -860,15 +864,17 @@ __global__ void __launch_bounds__(THREADS) exact_kernel(KArgs a) {
     const int dbias = a.dbias;
     const int top = 254 - dbias;
     L st;
-    for (uint32_t t0 = lo; t0 < hi; t0 += 64) {
+    for (uint32_t b = 0; b < nb; ++b) {
         uint32_t myid;
-        unsigned long long todo = __ballot(pending(t0 + lane, myid));
+        unsigned long long todo = __ballot(pending(b, myid));
         while (todo) {
             const int k = __ffsll((long long)todo) - 1;
             todo &= todo - 1ull;
             const uint32_t sid = (uint32_t)__builtin_amdgcn_readlane((int)myid, k);
             const uint4 r = a.win[sid];
-            const uint32_t ws = r.x, rows = r.y & kRowsMask;
+            // the window in whole 16-row steps: rows after its last loud step
+            // (the sequence's own, then its non-scoring padding) change nothing
+            const uint32_t ws = r.x, rows = ((r.y & kRowsMask) + 15u) & ~15u;
             const int tjbm = (int)(r.y >> 24) + a.tbm;
             int xb = kBase - tjbm;
             xb = xb < 0 ? 0 : xb;
@@ -900,12 +906,12 @@ __global__ void __launch_bounds__(THREADS) exact_kernel(KArgs a) {
             set_level();
             st.reset();
             // The window's residues come 1024 at a time, 16 per lane (windows
-            // start 16-byte aligned and hold a multiple of 8 rows, so the last
-            // lane's load stays in the sequence's padding); each step takes
-            // its 16 from one lane into scalar registers.  Scores are read
-            // one row ahead.
+            // start 16-byte aligned; sequences are stored in whole 16-residue
+            // steps); each step takes its 16 from one lane into scalar
+            // registers.  Scores are read
+            // kExactAhead rows ahead (the LDS latency is what bounds a row).
             uint4 blk = make_uint4(0u, 0u, 0u, 0u);
-            uint32_t ca[QX], cb[QX];
+            uint32_t cbuf[kExactAhead + 1][QX];
             for (uint32_t s = 0; s < rows; s += 16) {
                 if ((s & 1023u) == 0u) {
                     const uint32_t o = s + 16u * (uint32_t)lane;
@@ -922,15 +928,19 @@ __global__ void __launch_bounds__(THREADS) exact_kernel(KArgs a) {
                     return (word >> (8 * (k2 % 4))) & 0xffu;
                 };
                 // the step's rows; CHECK: the special states after each row
+                // the step's 16 rows; CHECK: the special states after each
                 auto step = [&](auto check_c) {
-                    st.load_row(T[0], T[1], T[2], xrow(0), ca);
+                    constexpr int N = 16;
+#pragma unroll
+                    for (int k2 = 0; k2 < kExactAhead; ++k2)
+                        st.load_row(T[0], T[1], T[2], xrow(k2), cbuf[k2]);
                     auto one_row = [&](auto k_c) {
                         constexpr int k2 = decltype(k_c)::value;
-                        uint32_t (&cur)[QX] = (k2 & 1) ? cb : ca;
-                        uint32_t (&nxt)[QX] = (k2 & 1) ? ca : cb;
-                        if (s + k2 >= rows) return;          // rows are a multiple of 8
-                        if constexpr (k2 + 1 < 16) st.load_row(T[0], T[1], T[2], xrow(k2 + 1), nxt);
-                        st.update(cur);
+                        constexpr int ahead = k2 + kExactAhead;
+                        if constexpr (ahead < N)
+                            st.load_row(T[0], T[1], T[2], xrow(ahead),
+                                        cbuf[ahead % (kExactAhead + 1)]);
+                        st.update(cbuf[k2 % (kExactAhead + 1)]);
                         if constexpr (decltype(check_c)::value) {
                             if (__any(above_level())) {
                                 int e2 = epoch_max();
@@ -955,15 +965,16 @@ __global__ void __launch_bounds__(THREADS) exact_kernel(KArgs a) {
                     };
                     [&]<int... R>(std::integer_sequence<int, R...>) {
                         (one_row(std::integral_constant<int, R>{}), ...);
-                    }(std::make_integer_sequence<int, 16>{});
+                    }(std::make_integer_sequence<int, N>{});
                 };
+                // with scB fixed; replayed from its starting cells, row by row
+                // with the special states, if a cell passed the level
                 uint32_t save[QX];
 #pragma unroll
                 for (int q = 0; q < QX; ++q) save[q] = st.R[q];
                 const uint32_t save_xe = st.xE;
                 step(std::false_type{});
                 if (__any(above_level())) {
-                    // replay the step from its starting cells, row by row
 #pragma unroll
                     for (int q = 0; q < QX; ++q) st.R[q] = save[q];
                     st.xE = save_xe;

@@ -553,6 +553,11 @@ def model_msv_window(prof, x, step, warm, T=None, end_short=0, align=16):
     ws = first - warm if first >= warm else 0
     ws -= ws % align
     we = last + step - end_short * step
+    if align == 16:
+        # the exact pass runs whole 16-row steps: the sequence's later rows,
+        # then non-scoring padding (sequences are stored in 16-row steps)
+        rows = rows + [20] * ((-len(rows)) % 16)
+        we = min(len(rows), ws + (we - ws + 15) // 16 * 16)
     cc, flag = exact_run(prof, rows[ws:we], tjbm)
     if flag or cc >= 255 - bias:
         return 255, 1

@@ -36,7 +36,7 @@ def test_closed_form_constants():
     assert q.tjb(3) == 3 and q.tjb(21) == 9 and q.tjb(45) == 12 and q.tjb(0) == 0
     assert q.tbm(1) == 0
     # Hand-evaluated: 3*log2(6) = 7.75, 3*log2(48*49/2) = 30.6, 3*log2(400*401/2) = 48.9,
-    # 3*log2(2400*2401/2) = 63.7
+    # 3*log2(2400*2401/2) = 64.4
     assert q.tbm(3) == 8 and q.tbm(48) == 31 and q.tbm(400) == 49 and q.tbm(2400) == 64
     # 3*log2(23/3) = 8.82, 3*log2(353/3) = 20.6, 3*log2(35003/3) = 40.6
     assert q.tjb(20) == 9 and q.tjb(350) == 21 and q.tjb(35000) == 41
