@@ -209,6 +209,22 @@ hmsv_status hmsv_ssv_score(const hmsv_profile *prof, const hmsv_db *db,
                            int8_t *score, uint8_t *flags, void *workspace,
                            const hmsv_plan *plan, hipStream_t stream);
 
+/* ---- MSV scoring without allocation ---------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  As
+ * hmsv_msv_score, but the workspace is the library's own device array of
+ * hmsv_workspace_bytes(HMSV_NOALLOC_MAX_SEQ) bytes (about 18 MB), one per
+ * GPU, held until the process ends.  The call allocates nothing: no
+ * hipMalloc, no host heap.  Every call on a GPU shares that GPU's array,
+ * so calls that overlap on one GPU (different streams, or different host
+ * threads) race and must be ordered by the caller; each call initialises
+ * what it reads.  Fails with HMSV_EUNSUPPORTED if the database has more
+ * than HMSV_NOALLOC_MAX_SEQ sequences, otherwise as hmsv_msv_score. */
+#define HMSV_NOALLOC_MAX_SEQ 1048576
+hmsv_status hmsv_msv_score_noalloc(const hmsv_profile *prof, const hmsv_db *db,
+                                   uint8_t *score, uint8_t *flags, const hmsv_plan *plan,
+                                   hipStream_t stream);
+
 /* ---- partial scoring (serving) -------------------------------------------
  * As hmsv_msv_score / hmsv_ssv_score, but only for the sequences at
  * positions [first, first + count) of the database's processing order

@@ -87,6 +87,9 @@ for _f in ("hmsv_msv_score", "hmsv_ssv_score"):
     getattr(_lib, _f).restype = ctypes.c_int
     getattr(_lib, _f).argtypes = [ctypes.POINTER(_CProfile), _P, _P, _P, _P,
                                   ctypes.POINTER(Plan), _P]
+_lib.hmsv_msv_score_noalloc.restype = ctypes.c_int
+_lib.hmsv_msv_score_noalloc.argtypes = [ctypes.POINTER(_CProfile), _P, _P, _P,
+                                        ctypes.POINTER(Plan), _P]
 for _f in ("hmsv_msv_score_range", "hmsv_ssv_score_range"):
     getattr(_lib, _f).restype = ctypes.c_int
     getattr(_lib, _f).argtypes = [ctypes.POINTER(_CProfile), _P, _i64, _i64, _P, _P, _P,
@@ -107,7 +110,8 @@ EXPORTED = ("hmsv_strerror", "hmsv_tbm", "hmsv_tjb", "hmsv_quantize", "hmsv_db_c
             "hmsv_msv_score", "hmsv_ssv_score",
             "hmsv_batch_create", "hmsv_batch_launch", "hmsv_batch_destroy",
             "hmsv_msv_score_range", "hmsv_ssv_score_range", "hmsv_db_order",
-            "hmsv_split_info", "hmsv_score_nats", "hmsv_gumbel_pvalue")
+            "hmsv_split_info", "hmsv_score_nats", "hmsv_gumbel_pvalue",
+            "hmsv_msv_score_noalloc")
 
 
 def _check(rc: int, what: str):
@@ -275,6 +279,32 @@ def _score(filt, profile: Profile, db: Database, score, flags, workspace, plan, 
 def msv_score(profile, db, score=None, flags=None, workspace=None, plan=None, stream=None):
     """MSV filter (paper Alg. 2): uint8 scores and overflow flags per sequence."""
     return _score("msv", profile, db, score, flags, workspace, plan, stream)
+
+
+NOALLOC_MAX_SEQ = 1 << 20
+
+
+def msv_score_noalloc(profile, db, score, flags, plan=None, stream=None):
+    """MSV filter with the library's own device workspace (no allocation;
+    see hmsv_msv_score_noalloc): score and flags are caller-owned uint8
+    device tensors of >= nseq entries.  Calls that overlap on one GPU race."""
+    dev = profile.device
+    n = db.nseq
+    if score.dtype != torch.uint8 or flags.dtype != torch.uint8:
+        raise TypeError("score/flags dtype")
+    if score.numel() < n or flags.numel() < n or not score.is_contiguous() \
+            or not flags.is_contiguous() or score.device != dev or flags.device != dev:
+        raise ValueError("score/flags must be contiguous on the profile's device with >= nseq "
+                         "entries")
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    pl = ctypes.byref(plan) if plan is not None else None
+    with torch.cuda.device(dev):
+        _check(_lib.hmsv_msv_score_noalloc(ctypes.byref(profile._c), db._h, score.data_ptr(),
+                                           flags.data_ptr(), pl,
+                                           ctypes.c_void_p(stream.cuda_stream)),
+               "hmsv_msv_score_noalloc")
+    return score, flags
 
 
 def ssv_score(profile, db, score=None, flags=None, workspace=None, plan=None, stream=None):

@@ -265,6 +265,34 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
     return HMSV_OK;
 }
 
+// ---- MSV scoring without allocation ---------------------------------------
+// The workspace of hmsv_msv_score_noalloc: a file-scope device array, one
+// copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it only stands in for the symbol);
+// it uses the device address hipGetSymbolAddress returns, looked up once
+// per device on the entry point's first call there.
+constexpr int64_t kNoAllocMaxSeq = (int64_t)1 << 20;
+constexpr size_t kScratchBytes = ws_bytes(kNoAllocMaxSeq);
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+hmsv_status scratch_ptr(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HMSV_EDEVICE;
+    if (dev < 0 || dev >= kMaxDevices) return HMSV_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HMSV_EDEVICE;
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return HMSV_OK;
+}
+
 }  // namespace
 
 namespace hmsv {
@@ -476,11 +504,14 @@ hmsv_status hmsv_default_plan(int32_t is_msv, int32_t M, hmsv_plan *plan) {
     for (int i = 0; i < kNumTuned; ++i)
         if (kTuned[i].is_msv == (is_msv ? 1 : 0)) idx[n++] = i;
     auto dist = [M](int b) { return std::fabs(std::log((double)b) - std::log((double)M)); };
-    std::stable_sort(idx, idx + n, [&](int a, int b) {
+    auto before = [&](int a, int b) {
         double da = dist(kTuned[a].bin), db = dist(kTuned[b].bin);
         if (da != db) return da < db;
         return kTuned[a].bin < kTuned[b].bin;
-    });
+    };
+    // insertion sort of the few bins (stable, and allocates nothing)
+    for (int t = 1; t < n; ++t)
+        for (int u = t; u > 0 && before(idx[u], idx[u - 1]); --u) std::swap(idx[u], idx[u - 1]);
     for (int t = 0; t < n; ++t) {
         const TunedPlan &tp = kTuned[idx[t]];
         int G = tp.G;
@@ -522,6 +553,17 @@ hmsv_status hmsv_msv_score(const hmsv_profile *prof, const hmsv_db *db, uint8_t 
                            uint8_t *flags, void *workspace, const hmsv_plan *plan,
                            hipStream_t stream) {
     return score_common(1, prof, db, 0, -1, score, flags, workspace, plan, stream);
+}
+
+hmsv_status hmsv_msv_score_noalloc(const hmsv_profile *prof, const hmsv_db *db,
+                                   uint8_t *score, uint8_t *flags, const hmsv_plan *plan,
+                                   hipStream_t stream) {
+    if (!db) return HMSV_EINVAL;
+    if (db->nseq > kNoAllocMaxSeq) return HMSV_EUNSUPPORTED;
+    void *ws = nullptr;
+    hmsv_status st = scratch_ptr(&ws);
+    if (st != HMSV_OK) return st;
+    return score_common(1, prof, db, 0, -1, score, flags, ws, plan, stream);
 }
 
 hmsv_status hmsv_ssv_score(const hmsv_profile *prof, const hmsv_db *db, int8_t *score,

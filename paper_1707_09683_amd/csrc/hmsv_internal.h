@@ -97,7 +97,7 @@ constexpr size_t kWsSlotOff = kWsSegOff + (size_t)kMaxSegs * sizeof(SeqRec);
 constexpr size_t kWsSegxOff = kWsSlotOff + (size_t)kMaxSplit * kSlotWords * 4;
 constexpr size_t kWsXImageOff = kWsSegxOff + (size_t)kMaxSegs * 8;
 constexpr size_t kWsWinOff = kWsXImageOff + 160 * 1024;
-inline size_t ws_bytes(int64_t nseq) { return kWsWinOff + 16 * (size_t)(nseq > 1 ? nseq : 1); }
+constexpr size_t ws_bytes(int64_t nseq) { return kWsWinOff + 16 * (size_t)(nseq > 1 ? nseq : 1); }
 
 typedef hipError_t (*LaunchFn)(const KArgs &, int waves_per_block, int blocks,
                                hipStream_t);
