@@ -144,6 +144,23 @@ def resources(jobs: int | None = None) -> str:
                    "-o", os.path.join(td, "k.o"), "-Rpass-analysis=kernel-resource-usage"]
             return subprocess.run(cmd, capture_output=True, text=True).stderr
 
+    def exact_unit():
+        with tempfile.TemporaryDirectory() as td:
+            cmd = [HIPCC, *COMMON, "--cuda-device-only", "-c", os.path.join(CSRC, "exact.hip"),
+                   "-o", os.path.join(td, "x.o"), "-Rpass-analysis=kernel-resource-usage"]
+            return subprocess.run(cmd, capture_output=True, text=True).stderr
+
+    exact = {}
+    cur = None
+    for m in rx.finditer(exact_unit()):
+        k, v = m.group(1), m.group(2)
+        if k == "Function Name":
+            mm = re.search(r"exact_kernelILi(\d+)ELi(\d+)E", v)
+            cur = int(mm.group(1)) if mm else None
+            if cur:
+                exact[cur] = {}
+        elif cur:
+            exact[cur][k] = int(v)
     with cf.ThreadPoolExecutor(max_workers=jobs or 8) as ex:
         for err in ex.map(one, units):
             cur = None
@@ -172,6 +189,15 @@ def resources(jobs: int | None = None) -> str:
             lines.append(f"| {filt} | {bins} | {G} | {Q} | {wpb} | {u.get('VGPRs')} | "
                          f"{u.get('TotalSGPRs')} | {u.get('ScratchSize [bytes/lane]')} | "
                          f"{occ_v} | {lds / 1024:.1f} | {blocks * wpb / 4:g} |")
+    lines += ["", "MSV exact pass (`exact_kernel<QX>`, 64-lane groups, blocks of 4 wavefronts; "
+              "QX = ceil((M + 1) / 128)):", "",
+              "| QX | M up to | VGPRs | SGPRs | scratch B/lane | waves/SIMD (VGPRs) | "
+              "LDS KiB/block |", "|---|---|---|---|---|---|---|"]
+    for qx in sorted(exact):
+        u = exact[qx]
+        lines.append(f"| {qx} | {128 * qx - 1} | {u.get('VGPRs')} | {u.get('TotalSGPRs')} | "
+                     f"{u.get('ScratchSize [bytes/lane]')} | {u.get('Occupancy [waves/SIMD]')} | "
+                     f"{plan_lds_bytes(64, qx) / 1024:.1f} |")
     return "\n".join(lines)
 
 
