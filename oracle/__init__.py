@@ -1,16 +1,20 @@
-"""CPU oracle for the MSV and SSV filters.
+"""CPU oracle for the MSV and SSV filters and the gapped P7Viterbi filter.
 
 TEST INFRASTRUCTURE ONLY.  This package is the plain, slow, obviously correct
 checker that the GPU library is measured against.  Only ``tests/``,
 ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
-import it.  It shares no code with the library: its own quantizer
-(``quant.py``, numpy float64) and its own scalar C filters (``filters.c``,
-built with gcc at -O2 without auto-vectorisation).
+import it.  It shares no code with the library: its own quantizers
+(``quant.py`` for MSV/SSV, ``p7.py`` for P7Viterbi, numpy float64) and its
+own scalar C filters (``filters.c``, ``p7viterbi.c``, built with gcc at -O2
+without auto-vectorisation).
 
 Every function here has been pinned against something other than itself in
 ``tests/test_oracle_pins.py``: closed-form constants, an unbounded-integer
 dynamic programme, enumeration of all segment paths on tiny inputs, the
-maximum over all diagonal segments, and special cases with known answers.
+maximum over all diagonal segments, and special cases with known answers;
+P7Viterbi in ``tests/test_oracle_p7_pins.py``: a hand-worked example,
+enumeration of every state path on tiny inputs, the no-gap case against an
+enumeration of ungapped multi-segment paths, closed forms and saturation.
 """
 from __future__ import annotations
 
@@ -21,21 +25,24 @@ import subprocess
 import numpy as np
 
 from . import quant as q
+from . import p7
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "filters.c")
+_SRCS = [_SRC, os.path.join(_HERE, "p7viterbi.c")]
 
 BASE = q.BASE
 
 
 def build(force: bool = False) -> str:
-    """Compile filters.c into liboracle.so with gcc (scalar, no vectorizer)."""
+    """Compile filters.c and p7viterbi.c into liboracle.so with gcc (scalar,
+    no vectorizer)."""
     if force or not os.path.exists(_LIB_PATH) or \
-            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            any(os.path.getmtime(_LIB_PATH) < os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fno-tree-vectorize", "-std=c11",
-                               "-shared", "-fPIC", "-pthread", "-o", tmp, _SRC])
+                               "-shared", "-fPIC", "-pthread", "-o", tmp, *_SRCS])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -55,6 +62,9 @@ def _load():
         lib.oracle_batch.argtypes = [i32, P, P, i32, i32, i32, i32, i32, P, P, P, P,
                                      i64, i32, P, P]
         lib.oracle_batch.restype = i32
+        lib.oracle_p7_seq.argtypes = [P, P, i32, i32, P, P, i64, P, P]
+        lib.oracle_p7_batch.argtypes = [P, P, i32, i32, P, P, P, P, i64, i32, P, P]
+        lib.oracle_p7_batch.restype = i32
         _lib = lib
     return _lib
 
@@ -123,4 +133,55 @@ def score_db(filt: str, prof: dict, res, offsets, ids=None, nthreads=None):
         raise RuntimeError("oracle thread start failed")
     if filt == "ssv":
         return score.view(np.int8), flag
+    return score, flag
+
+
+# ---- gapped Plan-7 Viterbi (P7Viterbi, paper Eq. 1) -------------------------
+def _p7_lenmodel(L) -> np.ndarray:
+    lm = p7.length_model(L)
+    return np.array([lm[k] for k in ("NN", "JJ", "CC", "NB", "JB", "CT", "EJ", "EC")],
+                    dtype=np.int32)
+
+
+def p7_seq(prof: dict, x):
+    """P7Viterbi score of one sequence: (int16 score, overflow flag)."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.uint8)
+    msc = np.ascontiguousarray(prof["msc"], dtype=np.int16)
+    tr = np.ascontiguousarray(prof["trans"], dtype=np.int16)
+    lm = _p7_lenmodel(len(x))
+    s = np.zeros(1, np.int16)
+    f = np.zeros(1, np.uint8)
+    lib.oracle_p7_seq(_ptr(msc), _ptr(tr), prof["M"], prof["tbm"], _ptr(lm), _ptr(x),
+                      len(x), _ptr(s), _ptr(f))
+    return int(s[0]), int(f[0])
+
+
+def p7_score_db(prof: dict, res, offsets, ids=None, nthreads=None):
+    """P7Viterbi scores of a concatenated database (int16 scores, uint8
+    flags, one per sequence; entries outside ``ids`` are 0)."""
+    lib = _load()
+    res = np.ascontiguousarray(res, dtype=np.uint8)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    n = len(offsets) - 1
+    lens = np.diff(offsets)
+    uniq = {int(L): _p7_lenmodel(int(L)) for L in np.unique(lens)}
+    lm = np.ascontiguousarray(np.stack([uniq[int(L)] for L in lens])
+                              if n else np.zeros((0, 8), np.int32), dtype=np.int32)
+    if ids is None:
+        order = np.argsort(-lens, kind="stable").astype(np.int64)
+    else:
+        ids = np.asarray(ids, dtype=np.int64)
+        order = ids[np.argsort(-lens[ids], kind="stable")]
+    order = np.ascontiguousarray(order)
+    score = np.zeros(n, np.int16)
+    flag = np.zeros(n, np.uint8)
+    msc = np.ascontiguousarray(prof["msc"], dtype=np.int16)
+    tr = np.ascontiguousarray(prof["trans"], dtype=np.int16)
+    nthreads = nthreads or max(1, min(16, os.cpu_count() or 1))
+    rc = lib.oracle_p7_batch(_ptr(msc), _ptr(tr), prof["M"], prof["tbm"], _ptr(lm),
+                             _ptr(res), _ptr(offsets), _ptr(order), len(order), nthreads,
+                             _ptr(score), _ptr(flag))
+    if rc != 0:
+        raise RuntimeError("oracle thread start failed")
     return score, flag

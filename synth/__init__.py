@@ -295,3 +295,77 @@ def random_db(rng, nseq: int, lo: int, hi: int) -> Database:
     L = rng.integers(lo, hi + 1, size=nseq).astype(np.int64)
     res, off = sample_residues(rng, L)
     return Database(res, off)
+
+
+# ---- gapped (Plan-7) profiles -------------------------------------------
+# Transition order per node k (transitions out of node k): M->M, M->I, M->D,
+# I->M, I->I, D->M, D->D.  The means below are typical of profile HMMs
+# built from curated families (matches dominate, gaps are rare and short);
+# they stand in for Pfam models, which are not available.
+TRANS_NAMES = ("MM", "MI", "MD", "IM", "II", "DM", "DD")
+_TRANS_MEAN_M = np.array([0.90, 0.05, 0.05])
+_TRANS_MEAN_I = np.array([0.60, 0.40])
+_TRANS_MEAN_D = np.array([0.70, 0.30])
+
+
+def sample_transitions(rng, M: int, conc: float = 20.0) -> np.ndarray:
+    """Per-node transition probabilities, float64 [M, 7] in TRANS_NAMES order.
+
+    Each node's M->{M,I,D}, I->{M,I} and D->{M,D} distributions are
+    Dirichlet(conc * mean).  The last node has no successor: its entries
+    are whatever was drawn (a profile's users ignore them)."""
+    out = np.empty((M, 7), dtype=np.float64)
+    out[:, 0:3] = rng.dirichlet(conc * _TRANS_MEAN_M, size=M)
+    out[:, 3:5] = rng.dirichlet(conc * _TRANS_MEAN_I, size=M)
+    out[:, 5:7] = rng.dirichlet(conc * _TRANS_MEAN_D, size=M)
+    return out
+
+
+def implant_gapped(rng, res, offsets, emis, trans, frac: float, max_len=None):
+    """Overwrite a segment of a fraction of the sequences with residues
+    emitted along a random path through a gapped profile: start at a random
+    node's match state, then follow the node's transition probabilities
+    (M->M/I/D, I->M/I, D->M/D), emitting a residue from the match
+    emissions at match states and from the background at insert states,
+    until the last node or ``max_len`` residues.  Returns the ids."""
+    M = emis.shape[0]
+    n = len(offsets) - 1
+    ids = np.flatnonzero(rng.random(n) < frac)
+    bg_cdf = np.cumsum(BG)
+    em_cdf = np.cumsum(emis, axis=1)
+    for sid in ids:
+        a, b = int(offsets[sid]), int(offsets[sid + 1])
+        L = b - a
+        if L == 0:
+            continue
+        cap = min(L, max_len or L)
+        k = int(rng.integers(0, M))
+        state = 0                              # 0 match, 1 insert, 2 delete
+        out = []
+        while len(out) < cap and k < M:
+            if state == 0:
+                out.append(int(np.searchsorted(em_cdf[k], rng.random() * em_cdf[k, -1],
+                                               side="right")))
+                p = trans[k, 0:3]
+            elif state == 1:
+                out.append(int(np.searchsorted(bg_cdf, rng.random() * bg_cdf[-1],
+                                               side="right")))
+                p = trans[k, 3:5]
+            else:
+                p = trans[k, 5:7]
+            u = rng.random() * p.sum()
+            nxt = int(np.searchsorted(np.cumsum(p), u, side="right"))
+            if state == 0:
+                state = (0, 1, 2)[min(nxt, 2)]
+            elif state == 1:
+                state = (0, 1)[min(nxt, 1)]
+            else:
+                state = (0, 2)[min(nxt, 1)]
+            if state != 1:
+                k += 1
+        ln = len(out)
+        if ln == 0:
+            continue
+        p0 = int(rng.integers(0, L - ln + 1))
+        res[a + p0: a + p0 + ln] = np.minimum(np.array(out), K - 1).astype(np.uint8)
+    return ids
