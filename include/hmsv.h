@@ -286,6 +286,75 @@ hmsv_status hmsv_batch_create(const hmsv_query *queries, int32_t nq, const hmsv_
 hmsv_status hmsv_batch_launch(hmsv_batch *batch, hipStream_t stream);
 void hmsv_batch_destroy(hmsv_batch *batch);
 
+/* ---- P7Viterbi: the gapped Plan-7 Viterbi filter ------------------------
+ * The pipeline's next stage (paper Sec. 2.1, Eq. 1): match, insert and
+ * delete cells per node with the Plan-7 special states N, B, E, C, J
+ * around them, in int16 saturating arithmetic (scores in 1/32 bit,
+ * HMSV_P7_UNITS per bit; -32768 is -inf).  Per row i and node j:
+ *   M[i][j] = msc_j(x_i) + max(M[i-1][j-1] + tMM, I[i-1][j-1] + tIM,
+ *                              D[i-1][j-1] + tDM, B[i-1] + tbm)
+ *   I[i][j] = max(M[i-1][j] + tMI, I[i-1][j] + tII)      (insert score 0)
+ *   D[i][j] = max(M[i][j-1] + tMD, D[i][j-1] + tDD)
+ * (transitions out of the node before j, or of j for tMI, tII), then
+ * E = max_j M[i][j] (local exit), J = max(J + loop, E - 32),
+ * C = max(C + loop, E - 32), N = N + loop, B = max(N + move, J + move),
+ * with loop = round(32 log2(L/(L+3))), move = round(32 log2(3/(L+3))) for a
+ * target of L residues (the MSV model's length model); row 0 has N = 0,
+ * B = move, all else -inf.  Score = C[L] + move, or 32767 with flags = 1
+ * once a row's E saturates at 32767. */
+#define HMSV_P7_UNITS 32
+#define HMSV_P7_MAX_M 2815  /* 64-lane groups of 22 registers: 28 table rows fill 160 KiB */
+
+/* Emissions [M][20] (as hmsv_quantize), transitions [M][7] float64
+ * probabilities out of each node in the order M->M, M->I, M->D, I->M,
+ * I->I, D->M, D->D, background [20] -> msc [32][M] int16 =
+ * round(32 log2(emis / bg)) (-32768 for zero emissions and codes 20..31),
+ * trans_out [7][M] int16 = round(32 log2 p) (-32768 for p = 0, and for
+ * every transition of node M, which has no successor and no insert state),
+ * tbm = round(32 log2(2 / (M (M + 1)))), all rounded half away from zero
+ * in float64.  Host memory.  Fails with HMSV_EINVAL on null pointers, M
+ * outside [1, HMSV_P7_MAX_M], negative or non-finite probabilities, or
+ * bg <= 0. */
+hmsv_status hmsv_p7_quantize(const double *emis, const double *trans, const double *bg,
+                             int32_t M, int16_t *msc, int16_t *trans_out, int32_t *tbm);
+
+/* The length model of a target of L residues: loop = round(32 log2(L /
+ * (L + 3))) (N->N, J->J, C->C; -32768 for L = 0), move = round(32 log2(3 /
+ * (L + 3))) (N->B, J->B, C->T).  hmsv_db_create stores it per record.
+ * HMSV_EINVAL on null pointers or L < 0. */
+hmsv_status hmsv_p7_length_model(int64_t L, int32_t *loop, int32_t *move);
+
+/* A quantized P7 profile; tables in caller-owned device memory as
+ * hmsv_p7_quantize writes them. */
+typedef struct {
+    int32_t M;
+    int32_t tbm;
+    const int16_t *msc;     /* device, [32][M] */
+    const int16_t *trans;   /* device, [7][M] */
+} hmsv_p7_profile;
+
+/* LDS bytes per workgroup of a P7 plan's kernel (0 for an invalid shape). */
+size_t hmsv_p7_lds_bytes(int32_t G, int32_t Q);
+
+/* Default P7 plan for M: the narrowest lane group (4..64 lanes) whose lanes
+ * hold the profile in at most 16 registers (22 for 64-lane groups), four
+ * wavefronts per block, persistent grid. */
+hmsv_status hmsv_p7_default_plan(int32_t M, hmsv_plan *plan);
+
+/* Scores every sequence of the database: score[i] int16, flags[i] = 1 on
+ * saturation (score 32767), both device arrays of nseq entries in the
+ * caller's original order.  workspace: hmsv_workspace_bytes(nseq) bytes,
+ * 256-byte aligned (calls sharing it must be ordered on one stream).  plan:
+ * NULL for the default (plans take 1..8 waves per block).  Lane groups take the records (longest first) in
+ * rounds, alternating direction; each sequence runs exactly its L rows.
+ * Asynchronous on the stream; allocates nothing.  Fails with HMSV_EINVAL on
+ * null pointers or a bad plan, HMSV_EUNSUPPORTED for M > HMSV_P7_MAX_M,
+ * HMSV_ENOKERNEL if the plan was not instantiated, HMSV_EDEVICE if the
+ * launch fails. */
+hmsv_status hmsv_p7_score(const hmsv_p7_profile *prof, const hmsv_db *db, int16_t *score,
+                          uint8_t *flags, void *workspace, const hmsv_plan *plan,
+                          hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

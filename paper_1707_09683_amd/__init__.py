@@ -104,6 +104,22 @@ _lib.hmsv_split_info.restype = ctypes.c_int
 _lib.hmsv_split_info.argtypes = [_P, _i64, _i64, _i32, _i32, ctypes.POINTER(Plan),
                                  ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
 
+class _CP7Profile(ctypes.Structure):
+    _fields_ = [("M", _i32), ("tbm", _i32), ("msc", _P), ("trans", _P)]
+
+
+_lib.hmsv_p7_quantize.restype = ctypes.c_int
+_lib.hmsv_p7_quantize.argtypes = [_P, _P, _P, _i32, _P, _P, ctypes.POINTER(_i32)]
+_lib.hmsv_p7_length_model.restype = ctypes.c_int
+_lib.hmsv_p7_length_model.argtypes = [_i64, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
+_lib.hmsv_p7_lds_bytes.restype = ctypes.c_size_t
+_lib.hmsv_p7_lds_bytes.argtypes = [_i32, _i32]
+_lib.hmsv_p7_default_plan.restype = ctypes.c_int
+_lib.hmsv_p7_default_plan.argtypes = [_i32, ctypes.POINTER(Plan)]
+_lib.hmsv_p7_score.restype = ctypes.c_int
+_lib.hmsv_p7_score.argtypes = [ctypes.POINTER(_CP7Profile), _P, _P, _P, _P,
+                               ctypes.POINTER(Plan), _P]
+
 EXPORTED = ("hmsv_strerror", "hmsv_tbm", "hmsv_tjb", "hmsv_quantize", "hmsv_db_create",
             "hmsv_db_destroy", "hmsv_db_nseq", "hmsv_db_residues", "hmsv_db_padded_rows",
             "hmsv_default_plan", "hmsv_plan_lds_bytes", "hmsv_workspace_bytes",
@@ -111,7 +127,8 @@ EXPORTED = ("hmsv_strerror", "hmsv_tbm", "hmsv_tjb", "hmsv_quantize", "hmsv_db_c
             "hmsv_batch_create", "hmsv_batch_launch", "hmsv_batch_destroy",
             "hmsv_msv_score_range", "hmsv_ssv_score_range", "hmsv_db_order",
             "hmsv_split_info", "hmsv_score_nats", "hmsv_gumbel_pvalue",
-            "hmsv_msv_score_noalloc")
+            "hmsv_msv_score_noalloc", "hmsv_p7_quantize", "hmsv_p7_length_model",
+            "hmsv_p7_lds_bytes", "hmsv_p7_default_plan", "hmsv_p7_score")
 
 
 def _check(rc: int, what: str):
@@ -310,6 +327,106 @@ def msv_score_noalloc(profile, db, score, flags, plan=None, stream=None):
 def ssv_score(profile, db, score=None, flags=None, workspace=None, plan=None, stream=None):
     """SSV filter (paper Alg. 7): int8 scores and overflow flags per sequence."""
     return _score("ssv", profile, db, score, flags, workspace, plan, stream)
+
+
+# ---- P7Viterbi (gapped Viterbi filter, paper Sec. 2.1, Eq. 1) ---------------
+
+P7_UNITS = 32
+P7_MAX_M = 2815
+P7_TRANSITIONS = ("MM", "MI", "MD", "IM", "II", "DM", "DD")
+
+
+def p7_quantize(emissions, transitions, bg):
+    """Host quantization of a gapped profile (hmsv_p7_quantize): emissions
+    [M, 20], transitions [M, 7] (order P7_TRANSITIONS), bg [20] probabilities
+    -> dict(msc int16 [32, M], trans int16 [7, M], tbm, M)."""
+    e = np.ascontiguousarray(emissions, dtype=np.float64)
+    t = np.ascontiguousarray(transitions, dtype=np.float64)
+    b = np.ascontiguousarray(bg, dtype=np.float64)
+    if e.ndim != 2 or e.shape[1] != K or b.shape != (K,) or t.shape != (e.shape[0], 7):
+        raise ValueError("emissions must be [M, 20], transitions [M, 7] and bg [20]")
+    M = e.shape[0]
+    msc = np.empty((KP, M), np.int16)
+    trans = np.empty((7, M), np.int16)
+    tb = _i32(0)
+    _check(_lib.hmsv_p7_quantize(_np_ptr(e), _np_ptr(t), _np_ptr(b), M, _np_ptr(msc),
+                                 _np_ptr(trans), ctypes.byref(tb)), "hmsv_p7_quantize")
+    return {"msc": msc, "trans": trans, "tbm": int(tb.value), "M": M}
+
+
+def p7_length_model(L: int):
+    """(loop, move) of the P7 length model for a target of L residues."""
+    lo, mv = _i32(0), _i32(0)
+    _check(_lib.hmsv_p7_length_model(int(L), ctypes.byref(lo), ctypes.byref(mv)),
+           "hmsv_p7_length_model")
+    return int(lo.value), int(mv.value)
+
+
+def p7_lds_bytes(G, Q) -> int:
+    """LDS bytes per workgroup of the P7 kernel (G, Q); 0 if invalid."""
+    return int(_lib.hmsv_p7_lds_bytes(int(G), int(Q)))
+
+
+def p7_default_plan(M: int) -> Plan:
+    p = Plan()
+    _check(_lib.hmsv_p7_default_plan(int(M), ctypes.byref(p)), "hmsv_p7_default_plan")
+    return p
+
+
+class P7Profile:
+    """A quantized gapped profile with its tables in device memory."""
+
+    def __init__(self, msc: torch.Tensor, trans: torch.Tensor, tbm: int):
+        if msc.dtype != torch.int16 or trans.dtype != torch.int16:
+            raise TypeError("msc and trans must be int16")
+        if msc.dim() != 2 or msc.shape[0] != KP or trans.shape != (7, msc.shape[1]):
+            raise ValueError("msc must be [32, M] and trans [7, M]")
+        if msc.device != trans.device:
+            raise ValueError("tables must be on one device")
+        self.msc = msc.contiguous()
+        self.trans = trans.contiguous()
+        self.M = int(msc.shape[1])
+        self.tbm = int(tbm)
+        self.device = self.msc.device
+        self._c = _CP7Profile(self.M, self.tbm, self.msc.data_ptr(), self.trans.data_ptr())
+
+    @classmethod
+    def from_probabilities(cls, emissions, transitions, bg, device="cuda"):
+        q = p7_quantize(emissions, transitions, bg)
+        return cls(torch.from_numpy(q["msc"]).to(device), torch.from_numpy(q["trans"]).to(device),
+                   q["tbm"])
+
+
+def p7_score(profile: P7Profile, db: Database, score=None, flags=None, workspace=None,
+             plan=None, stream=None):
+    """P7Viterbi filter: int16 scores (1/32 bit) and saturation flags per
+    sequence, in the database's original order."""
+    dev = profile.device
+    n = db.nseq
+    if score is None:
+        score = torch.empty(n, dtype=torch.int16, device=dev)
+    if flags is None:
+        flags = torch.empty(n, dtype=torch.uint8, device=dev)
+    if workspace is None:
+        workspace = new_workspace(dev, n)
+    if score.dtype != torch.int16 or flags.dtype != torch.uint8:
+        raise TypeError("score must be int16 and flags uint8")
+    if score.numel() < n or flags.numel() < n or not score.is_contiguous() \
+            or not flags.is_contiguous():
+        raise ValueError("score/flags must be contiguous with >= nseq entries")
+    if workspace.numel() * workspace.element_size() < workspace_bytes(n):
+        raise ValueError("workspace too small")
+    for t in (score, flags, workspace):
+        if t.device != dev:
+            raise ValueError("all tensors must be on the profile's device")
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    pl = ctypes.byref(plan) if plan is not None else None
+    with torch.cuda.device(dev):
+        _check(_lib.hmsv_p7_score(ctypes.byref(profile._c), db._h, score.data_ptr(),
+                                  flags.data_ptr(), workspace.data_ptr(), pl,
+                                  ctypes.c_void_p(stream.cuda_stream)), "hmsv_p7_score")
+    return score, flags
 
 
 def score_nats(filt, M, score, flags, lengths):

@@ -36,6 +36,8 @@ COMMON = ["-O3", f"--offload-arch={ARCH}", "-std=c++20", "-fPIC",
 # 160 KiB, which caps G = 64 at Q = 30 (profiles up to 3840 nodes).
 GROUPS = ((1, 32), (2, 32), (4, 32), (8, 32), (16, 32), (32, 32), (64, 30))
 QCHUNK = 4
+# P7Viterbi kernels: (G, largest Q); 28 table rows cap G = 64 at Q = 22.
+P7_GROUPS = ((4, 16), (8, 16), (16, 16), (32, 16), (64, 22))
 
 
 def kernel_units():
@@ -92,6 +94,13 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
     host_cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, "hmsv_host.cpp"),
                 "-o", host_obj]
     tasks.append((host_cmd, host_obj, _deps_hash(["host"])))
+    for G, qmax in P7_GROUPS:
+        for lo in range(1, qmax + 1, QCHUNK):
+            hi = min(qmax, lo + QCHUNK - 1)
+            obj = os.path.join(OBJ, f"p7_g{G}_q{lo}_{hi}.o")
+            defs = [f"-DHMSV_G={G}", f"-DHMSV_QLO={lo}", f"-DHMSV_QHI={hi}"]
+            cmd = [HIPCC, *COMMON, *defs, "-c", os.path.join(CSRC, "p7.hip"), "-o", obj]
+            tasks.append((cmd, obj, _deps_hash(["p7", *defs])))
     exact_obj = os.path.join(OBJ, "exact.o")
     tasks.append(([HIPCC, *COMMON, "-c", os.path.join(CSRC, "exact.hip"), "-o", exact_obj],
                   exact_obj, _deps_hash(["exact"])))

@@ -56,9 +56,9 @@ constexpr int kTec = 3;
 
 // The lane's view of the profile's LDS image (lds_layout in
 // hmsv_internal.h describes the image).
-template <int G, int Q>
+template <int G, int Q, int ROWS = kRows>
 struct Layout {
-    static constexpr LdsLayout D = lds_layout(G, Q);
+    static constexpr LdsLayout D = lds_layout(G, Q, ROWS);
     static constexpr int W = 4;                       // dwords per chunk read
     static constexpr int NF = D.NF;
     static constexpr int R = D.R;
@@ -399,7 +399,7 @@ filter_kernel(KArgs a) {
             d[0] = *(const uint32_t *)(a.res + o);
         }
     };
-    uint4 ra;                    // record A: off, rows | tjb << 24, id, first residues
+    uint4 ra;                    // record A: off, rows | tjb << 24, id, length
     uint4 ra16;                  // record A's first sixteen residues (K > 1)
     int qa, qc;                  // records of A and of the claimed position (kNone: none)
     uint32_t pend_b = 0;
@@ -412,12 +412,11 @@ filter_kernel(KArgs a) {
         seq_end = valid ? r.x + rows : a.pad_off;
         id = r.z;
         tjbm = (int)(r.y >> 24) + a.tbm;
+        static_assert(K == 4 || K == 2, "residues come 16 or 8 per load");
         if constexpr (K == 4) {
             wv[0] = r16.x; wv[1] = r16.y; wv[2] = r16.z; wv[3] = r16.w;
-        } else if constexpr (K == 2) {
-            wv[0] = r16.x; wv[1] = r16.y;
         } else {
-            wv[0] = r.w;
+            wv[0] = r16.x; wv[1] = r16.y;
         }
     };
 

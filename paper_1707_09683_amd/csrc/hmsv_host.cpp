@@ -29,6 +29,7 @@ struct hmsv_db {
     int64_t rows = 0;
     uint8_t *d_res = nullptr;
     SeqRec *d_seqs = nullptr;
+    uint32_t *d_p7len = nullptr;   // per record: P7 length model, loop | move << 16
     uint32_t pad_off = 0;
     int device = 0;
     std::vector<int64_t> order;   // processing order -> original index
@@ -47,9 +48,32 @@ double rhaz(double v) {
 // Third-bit cost of a probability p in (0, 1]: -round(3 log2 p).
 int32_t third_bit_cost(double p) { return (int32_t)(-rhaz(3.0 * std::log2(p))); }
 
+// P7Viterbi score of a probability (or odds ratio) p: round(32 log2 p),
+// clamped to int16; -32768 (-inf) for p = 0.
+constexpr int kP7Units = 32;
+int32_t p7_score(double p) {
+    if (!(p > 0.0)) return -32768;
+    double v = rhaz((double)kP7Units * std::log2(p));
+    return (int32_t)std::max(-32768.0, std::min(32767.0, v));
+}
+
+// The P7Viterbi length model of a target of L residues: N/J/C loops and
+// N->B, J->B, C->T moves, packed as two int16.
+uint32_t p7_lenmodel(int64_t L) {
+    const int32_t loop = L > 0 ? p7_score((double)L / ((double)L + 3.0)) : -32768;
+    const int32_t move = p7_score(3.0 / ((double)L + 3.0));
+    return (uint32_t)(uint16_t)(int16_t)loop | ((uint32_t)(uint16_t)(int16_t)move << 16);
+}
+
 struct Registry {
     std::vector<KernelEntry> entries;
     ExactLaunchFn exact[kMaxExactQ + 1] = {};
+    std::vector<P7KernelEntry> p7;
+    const P7KernelEntry *find_p7(int G, int Q) const {
+        for (const auto &e : p7)
+            if (e.G == G && e.Q == Q) return &e;
+        return nullptr;
+    }
     const KernelEntry *find(int is_msv, int G, int Q) const {
         for (const auto &e : entries)
             if (e.is_msv == is_msv && e.G == G && e.Q == Q) return &e;
@@ -301,6 +325,11 @@ int register_kernels(const KernelEntry *entries, int n) {
     return n;
 }
 
+int register_p7_kernels(const P7KernelEntry *entries, int n) {
+    registry().p7.insert(registry().p7.end(), entries, entries + n);
+    return n;
+}
+
 int register_exact(int qx, ExactLaunchFn fn) {
     if (qx >= 1 && qx <= kMaxExactQ) registry().exact[qx] = fn;
     return qx;
@@ -422,6 +451,7 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
     std::stable_sort(order.begin(), order.end(),
                      [&](int64_t a, int64_t b) { return len[a] > len[b]; });
     std::vector<SeqRec> recs((size_t)nseq);
+    std::vector<uint32_t> p7len((size_t)std::max<int64_t>(1, nseq), 0u);
     uint64_t total = 0, rows = 0;
     std::vector<int64_t> cum_rows((size_t)nseq + 1, 0);
     for (int64_t t = 0; t < nseq; ++t) {
@@ -431,6 +461,7 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
         recs[t].off = (uint32_t)total;
         recs[t].rt = (uint32_t)r | ((uint32_t)hmsv_tjb(len[i]) << 24);
         recs[t].id = (uint32_t)i;
+        p7len[t] = p7_lenmodel(len[i]);
 
         // 16-byte aligned; the rows rounded up to 16, then 16 bytes of code 20
         // (narrow lane groups run 16 rows per step and read past the end)
@@ -447,7 +478,7 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
         const uint8_t *p = res + offsets[i];
         uint8_t *d = packed.data() + recs[t].off;
         for (int64_t k = 0; k < len[i]; ++k) d[k] = p[k] < HMSV_K ? p[k] : kInvalidCode;
-        std::memcpy(&recs[t].first, d, sizeof(uint32_t));
+        recs[t].len = (uint32_t)len[i];
         std::memcpy(recs[t].first16, d, 4 * sizeof(uint32_t));
     }
     hmsv_db *db = new (std::nothrow) hmsv_db;
@@ -470,9 +501,15 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
         delete db;
         return HMSV_ENOMEM;
     }
+    if (hipMalloc(&db->d_p7len, sizeof(uint32_t) * p7len.size()) != hipSuccess) {
+        hmsv_db_destroy(db);
+        return HMSV_ENOMEM;
+    }
     if (hipMemcpy(db->d_res, packed.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
         (nseq > 0 && hipMemcpy(db->d_seqs, recs.data(), sizeof(SeqRec) * (size_t)nseq,
-                               hipMemcpyHostToDevice) != hipSuccess)) {
+                               hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(db->d_p7len, p7len.data(), sizeof(uint32_t) * p7len.size(),
+                  hipMemcpyHostToDevice) != hipSuccess) {
         hmsv_db_destroy(db);
         return HMSV_EDEVICE;
     }
@@ -484,6 +521,7 @@ void hmsv_db_destroy(hmsv_db *db) {
     if (!db) return;
     if (db->d_res) hipFree(db->d_res);
     if (db->d_seqs) hipFree(db->d_seqs);
+    if (db->d_p7len) hipFree(db->d_p7len);
     delete db;
 }
 
@@ -612,6 +650,115 @@ hmsv_status hmsv_split_info(const hmsv_db *db, int64_t first, int64_t count, int
     *nsplit = a.nsplit;
     *nsegs = a.nsegs;
     *seg_rows = a.seg_rows;
+    return HMSV_OK;
+}
+
+// ---- P7Viterbi -------------------------------------------------------------
+
+hmsv_status hmsv_p7_quantize(const double *emis, const double *trans, const double *bg,
+                             int32_t M, int16_t *msc, int16_t *trans_out, int32_t *tbm) {
+    if (!emis || !trans || !bg || !msc || !trans_out || !tbm) return HMSV_EINVAL;
+    if (M < 1 || M > HMSV_P7_MAX_M) return HMSV_EINVAL;
+    for (int x = 0; x < HMSV_K; ++x)
+        if (!(bg[x] > 0.0) || !std::isfinite(bg[x])) return HMSV_EINVAL;
+    for (int64_t i = 0; i < (int64_t)M * HMSV_K; ++i)
+        if (!(emis[i] >= 0.0) || !std::isfinite(emis[i])) return HMSV_EINVAL;
+    for (int64_t i = 0; i < (int64_t)M * 7; ++i)
+        if (!(trans[i] >= 0.0) || !std::isfinite(trans[i])) return HMSV_EINVAL;
+    for (int x = 0; x < HMSV_KP; ++x)
+        for (int k = 0; k < M; ++k)
+            msc[(size_t)x * M + k] = (int16_t)(x < HMSV_K
+                ? p7_score(emis[(size_t)k * HMSV_K + x] / bg[x]) : -32768);
+    for (int t = 0; t < 7; ++t)
+        for (int k = 0; k < M; ++k)
+            trans_out[(size_t)t * M + k] = (int16_t)p7_score(trans[(size_t)k * 7 + t]);
+    // node M has no successor and no insert state
+    for (int t = 0; t < 7; ++t) trans_out[(size_t)t * M + M - 1] = (int16_t)-32768;
+    *tbm = p7_score(2.0 / ((double)M * ((double)M + 1.0)));
+    return HMSV_OK;
+}
+
+hmsv_status hmsv_p7_length_model(int64_t L, int32_t *loop, int32_t *move) {
+    if (!loop || !move || L < 0) return HMSV_EINVAL;
+    const uint32_t v = p7_lenmodel(L);
+    *loop = (int32_t)(int16_t)(v & 0xffffu);
+    *move = (int32_t)(int16_t)(v >> 16);
+    return HMSV_OK;
+}
+
+size_t hmsv_p7_lds_bytes(int32_t G, int32_t Q) {
+    if (G < 1 || G > 64 || (64 % G) != 0 || Q < 1) return 0;
+    return p7_lds_bytes(G, Q);
+}
+
+hmsv_status hmsv_p7_default_plan(int32_t M, hmsv_plan *plan) {
+    if (!plan || M < 1) return HMSV_EINVAL;
+    if (M > HMSV_P7_MAX_M) return HMSV_EUNSUPPORTED;
+    // the narrowest group whose lanes hold the profile in at most 16
+    // registers (22 for 64-lane groups: profiles beyond 2047 nodes)
+    for (int G : {4, 8, 16, 32, 64}) {
+        const int Q = (M + 1 + 2 * G - 1) / (2 * G);
+        if (Q > (G == 64 ? 22 : 16) || p7_lds_bytes(G, Q) > (size_t)kLdsBytes) continue;
+        if (!registry().find_p7(G, Q)) continue;
+        plan->G = G;
+        plan->Q = Q;
+        plan->waves_per_block = 4;
+        plan->blocks = 0;
+        return HMSV_OK;
+    }
+    return HMSV_ENOKERNEL;
+}
+
+hmsv_status hmsv_p7_score(const hmsv_p7_profile *prof, const hmsv_db *db, int16_t *score,
+                          uint8_t *flags, void *workspace, const hmsv_plan *plan_in,
+                          hipStream_t stream) {
+    if (!prof || !db || !score || !flags || !workspace || !prof->msc || !prof->trans)
+        return HMSV_EINVAL;
+    if (prof->M < 1) return HMSV_EINVAL;
+    if (prof->M > HMSV_P7_MAX_M) return HMSV_EUNSUPPORTED;
+    if (((uintptr_t)workspace & 255u) != 0) return HMSV_EINVAL;
+    hmsv_plan plan;
+    if (plan_in) {
+        plan = *plan_in;
+    } else {
+        hmsv_status st = hmsv_p7_default_plan(prof->M, &plan);
+        if (st != HMSV_OK) return st;
+    }
+    if (plan.G < 1 || plan.G > 64 || (64 % plan.G) != 0 || plan.Q < 1 ||
+        plan_nodes(plan.G, plan.Q) < prof->M || plan.blocks < 0 ||
+        plan.waves_per_block < 1 || plan.waves_per_block > 8)
+        return HMSV_EINVAL;
+    if (p7_lds_bytes(plan.G, plan.Q) > (size_t)kLdsBytes) return HMSV_EUNSUPPORTED;
+    const P7KernelEntry *e = registry().find_p7(plan.G, plan.Q);
+    if (!e) return HMSV_ENOKERNEL;
+    if (db->nseq == 0) return HMSV_OK;
+    int blocks = plan.blocks;
+    if (blocks == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return HMSV_EDEVICE;
+        const int per_cu = e->occupancy(plan.waves_per_block);
+        if (per_cu <= 0) return HMSV_EDEVICE;
+        blocks = per_cu * cus;
+        const int64_t groups_per_block = (int64_t)plan.waves_per_block * (64 / plan.G);
+        const int64_t need = (db->nseq + groups_per_block - 1) / groups_per_block;
+        if (need < blocks) blocks = (int)need;
+    }
+    P7Args a{};
+    a.msc = prof->msc;
+    a.trans = prof->trans;
+    a.M = prof->M;
+    a.tbm = prof->tbm;
+    a.res = db->d_res;
+    a.seqs = db->d_seqs;
+    a.lenmodel = db->d_p7len;
+    a.nseq = (int32_t)db->nseq;
+    a.pad_off = db->pad_off;
+    a.score = score;
+    a.flag = flags;
+    a.image = (uint32_t *)((char *)workspace + kWsCounterBytes);
+    if (e->launch(a, plan.waves_per_block, blocks, stream) != hipSuccess) return HMSV_EDEVICE;
     return HMSV_OK;
 }
 

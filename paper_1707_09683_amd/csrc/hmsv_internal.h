@@ -22,7 +22,8 @@ struct SeqRec {
     uint32_t id;        // index in the caller's original order; for a
                         // segment of a split sequence, kSegBit | its
                         // index among the call's segments
-    uint32_t first;     // its first four residues (also first16[0])
+    uint32_t len;       // its length in residues (database records; a
+                        // segment's record holds its first four residues)
     uint32_t first16[4];  // its first sixteen residues
 };
 static_assert(sizeof(SeqRec) == 32, "records are two 16-byte loads");
@@ -112,6 +113,11 @@ struct KernelEntry {
     OccupancyFn occupancy;
 };
 
+// P7Viterbi's LDS image rows: 21 of match emissions (residue rows, row 20 =
+// -inf), then 7 of transitions (see P7Args).
+constexpr int kP7EmisRows = kRows;
+constexpr int kP7Rows = kRows + 7;
+
 // The profile's LDS image: kRows table rows of RS dwords.  A lane reads its
 // Q score pairs in chunks of 4 dwords (ds_read_b128), then a 2-dword and/or
 // a 1-dword tail; a partial last chunk is instead read whole (its unused
@@ -135,11 +141,11 @@ struct LdsLayout {
 
 constexpr int lds_copies(int G, int w) { return 64 / (G * w) > 1 ? 64 / (G * w) : 1; }
 
-constexpr LdsLayout lds_layout(int G, int Q) {
+constexpr LdsLayout lds_layout(int G, int Q, int rows = kRows) {
     LdsLayout L{};
     L.CW = lds_copies(G, 4) * G * 4;
     int nf = Q / 4, r = Q % 4;
-    L.WIDE = r != 0 && (size_t)kRows * (size_t)(nf + 1) * (size_t)L.CW * 4 <= kLdsBytes;
+    L.WIDE = r != 0 && (size_t)rows * (size_t)(nf + 1) * (size_t)L.CW * 4 <= kLdsBytes;
     L.NF = L.WIDE ? nf + 1 : nf;
     L.R = L.WIDE ? 0 : r;
     L.OFF2 = L.NF * L.CW;
@@ -149,10 +155,45 @@ constexpr LdsLayout lds_layout(int G, int Q) {
 }
 
 inline size_t lds_bytes(int G, int Q) { return (size_t)kRows * lds_layout(G, Q).RS * 4; }
+inline size_t p7_lds_bytes(int G, int Q) {
+    return (size_t)kP7Rows * lds_layout(G, Q, kP7Rows).RS * 4;
+}
 
 // A group of G lanes with Q registers covers nodes 1..2GQ-1 (slot 0 is a
 // dummy -inf node).
 inline int64_t plan_nodes(int G, int Q) { return (int64_t)2 * G * Q - 1; }
+
+// ---- P7Viterbi (gapped Plan-7 Viterbi) -------------------------------------
+// The transition rows of the LDS image, each laid out as the MSV/SSV image
+// (lds_layout with kP7Rows rows): slot s holds the transition used by node
+// s's cells, so the ones into node s from node s-1 are stored shifted by
+// one slot.
+enum P7TransRow : int { kP7MMp = 0, kP7IMp, kP7DMp, kP7MI, kP7II, kP7MDp, kP7DDp };
+
+struct P7Args {
+    const int16_t *msc;    // [32][M] match emission scores (device)
+    const int16_t *trans;  // [7][M] MM, MI, MD, IM, II, DM, DD out of each node (device)
+    int32_t M;
+    int32_t tbm;           // B->M_k
+    const uint8_t *res;    // packed residues
+    const SeqRec *seqs;    // records in processing order
+    const uint32_t *lenmodel;  // per record: loop (low 16 bits) | move << 16 (int16 each)
+    int32_t nseq;
+    uint32_t pad_off;
+    int16_t *score;
+    uint8_t *flag;
+    uint32_t *image;       // the LDS image (workspace)
+};
+
+constexpr int kMaxP7G = 64;
+typedef hipError_t (*P7LaunchFn)(const P7Args &, int waves_per_block, int blocks, hipStream_t);
+struct P7KernelEntry {
+    int G;
+    int Q;
+    P7LaunchFn launch;
+    OccupancyFn occupancy;
+};
+int register_p7_kernels(const P7KernelEntry *entries, int n);
 
 // Each kernel translation unit registers its instantiations at load time.
 int register_kernels(const KernelEntry *entries, int n);

@@ -1,0 +1,378 @@
+// P7Viterbi (gapped Plan-7 Viterbi) filter kernel for gfx950.
+//
+// What it computes (paper Sec. 2.1, Eq. 1, with the Plan-7 special states
+// N, B, E, C, J of the DP matrix's flanks), in int16 saturating arithmetic
+// with -32768 as -inf, for residues x_1..x_L and nodes j = 1..M:
+//   M[i][j] = msc_j(x_i) + max(M[i-1][j-1] + tMM, I[i-1][j-1] + tIM,
+//                              D[i-1][j-1] + tDM, B[i-1] + tBM)
+//   I[i][j] = max(M[i-1][j] + tMI, I[i-1][j] + tII)        (insert score 0)
+//   D[i][j] = max(M[i][j-1] + tMD, D[i][j-1] + tDD)
+// then per row E = max_j M, J = max(J + tJJ, E + tEJ), C = max(C + tCC,
+// E + tEC), N = N + tNN, B = max(N + tNB, J + tJB); score = C[L] + tCT, or
+// 32767 with the overflow flag once a row's E saturates.
+//
+// Mapping (as the MSV/SSV kernel): a lane group of G lanes aligns one
+// sequence; each lane holds Q registers of two int16 cells for each of M,
+// I and D, striped (register q, element e = lane e/2, half e%2, is slot
+// q + Q e; slot 0 is a dummy node whose emissions and transitions are -inf,
+// so every value it holds reaches a real node only through a -inf
+// transition).  Packed saturating adds (v_pk_add_i16 clamp) and maxima
+// (v_pk_max_i16) update two cells per instruction.
+//
+// Per row: the M and I cells and a first pass of D within each element
+// (D's chain crosses into the next element unknown, taken as -inf); then
+// the chains are completed Farrar-style ("lazy F"): each element takes the
+// last D of the element before it (one DPP shift) and carries it along its
+// slots, max-ing it in, until no element's last D changes (max and a
+// saturating add of a fixed score commute, so the result is the sequential
+// chain's).  Scores come from LDS: 21 rows of match emissions by residue
+// and 7 rows of transitions, in the MSV image's conflict-free layout.
+// The special states are updated once per row from the group's maximum.
+//
+// Sequences are dealt out statically: lane group g of N takes records g,
+// 2N - 1 - g, 2N + g, ... (records run longest first, so alternating the
+// direction evens the groups' totals); the next record is loaded while the
+// current one runs.  A sequence runs exactly L rows: the rows of the last
+// 16-residue step past L leave the special states untouched.
+#pragma once
+#include <utility>
+#include "filter_kernel.hpp"
+
+namespace hmsv {
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ s16x2 as_s16x2(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
+__device__ __forceinline__ uint32_t s16_bits(s16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ s16x2 adds(s16x2 a, s16x2 b) { return __builtin_elementwise_add_sat(a, b); }
+__device__ __forceinline__ s16x2 smax(s16x2 a, s16x2 b) { return __builtin_elementwise_max(a, b); }
+__device__ __forceinline__ s16x2 splat16(int v) { return s16x2{(short)v, (short)v}; }
+
+constexpr int kP7Neg = -32768;
+constexpr int kP7Pos = 32767;
+constexpr int kP7Half = -32;          // E->J and E->C: 32 log2(1/2)
+__device__ __forceinline__ int sat16(int v) { return v < kP7Neg ? kP7Neg : (v > kP7Pos ? kP7Pos : v); }
+
+// Score of table row r (0..20 emissions by residue, 21.. transitions) at
+// slot s (node s; slot 0 is the dummy).
+__device__ __forceinline__ int p7_slot_score(const P7Args &a, int r, int s) {
+    const int M = a.M;
+    if (r < kP7EmisRows) {
+        if (s < 1 || s > M || r == kInvalidCode) return kP7Neg;
+        return a.msc[r * M + s - 1];
+    }
+    // transitions: MMp, IMp, DMp, MDp, DDp come from node s - 1; MI, II
+    // from node s (their table rows: MM 0, MI 1, MD 2, IM 3, II 4, DM 5, DD 6)
+    const int t = r - kP7EmisRows;
+    const int from = (t == kP7MI || t == kP7II) ? s : s - 1;
+    if (from < 1 || from > M) return kP7Neg;
+    const int row = t == kP7MMp ? 0 : t == kP7IMp ? 3 : t == kP7DMp ? 5 : t == kP7MI ? 1
+                  : t == kP7II ? 4 : t == kP7MDp ? 2 : 6;
+    return a.trans[row * M + from - 1];
+}
+
+// The LDS image (kP7Rows rows of the lds_layout(G, Q) shape), one dword per
+// thread.
+template <int G, int Q>
+__global__ void __launch_bounds__(256) p7_prep_kernel(P7Args a) {
+    constexpr LdsLayout D = lds_layout(G, Q, kP7Rows);
+    const int idx = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (idx >= kP7Rows * D.RS) return;
+    const int x = idx / D.RS;
+    int rem = idx - x * D.RS;
+    int w, q0;
+    if (rem < D.OFF2) {
+        const int ch = rem / D.CW;
+        rem -= ch * D.CW;
+        w = 4;
+        q0 = ch * 4;
+    } else if (rem < D.OFF1) {
+        rem -= D.OFF2;
+        w = 2;
+        q0 = D.NF * 4;
+    } else {
+        rem -= D.OFF1;
+        w = 1;
+        q0 = D.NF * 4 + ((D.R & 2) ? 2 : 0);
+    }
+    rem %= G * w;
+    const int jj = rem / w;
+    const int qq = q0 + (rem - jj * w);
+    const int s0 = qq + Q * (2 * jj);
+    uint32_t v = 0u;
+    if (qq < Q) {
+        const uint32_t lo = (uint16_t)(short)p7_slot_score(a, x, s0);
+        const uint32_t hi = (uint16_t)(short)p7_slot_score(a, x, s0 + Q);
+        v = lo | (hi << 16);
+    }
+    a.image[idx] = v;
+}
+
+template <int G, int Q, int THREADS>
+__global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
+    using Lay = Layout<G, Q, kP7Rows>;
+    constexpr int RS = Lay::RS;
+    extern __shared__ uint32_t lds[];
+    {
+        const uint4 *src = (const uint4 *)a.image;
+        uint4 *dst = (uint4 *)lds;
+        constexpr int n16 = kP7Rows * RS / 4;
+        for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int j = lane % G;
+    const bool gstart = j == 0;
+    const uint32_t *T[3] = {lds + Lay::lane_off(lane, 4),
+                            lds + Lay::OFF2 + Lay::lane_off(lane, 2),
+                            lds + Lay::OFF1 + Lay::lane_off(lane, 1)};
+    // Dwords of table row r for this lane: chunk ch of 4 (registers
+    // 4ch..4ch+3), the 2-dword tail (registers Q2, Q2+1), the 1-dword tail
+    // (register Q1).
+    auto chunk = [&](uint32_t r, int ch) -> uint4 {
+        return *(const uint4 *)((const char *)T[0] + r * (uint32_t)(RS * 4) + ch * Lay::CW * 4);
+    };
+    auto tail2 = [&](uint32_t r) -> uint2 {
+        return *(const uint2 *)((const char *)T[1] + r * (uint32_t)(RS * 4));
+    };
+    auto tail1 = [&](uint32_t r) -> uint32_t {
+        return *(const uint32_t *)((const char *)T[2] + r * (uint32_t)(RS * 4));
+    };
+    auto comp = [](const uint4 &v, int u) -> uint32_t {
+        return u == 0 ? v.x : u == 1 ? v.y : u == 2 ? v.z : v.w;
+    };
+    constexpr uint32_t rT = kP7EmisRows;     // first transition row
+
+    const int ngroups = (int)(gridDim.x * (blockDim.x / G));
+    const int gid = (int)(blockIdx.x * (blockDim.x / G) + threadIdx.x / G);
+    const int nseq = a.nseq;
+    // the k-th record of this group: rounds of ngroups, direction alternating
+    auto record_of = [&](int k) -> int {
+        const int base = k * ngroups;
+        return base + ((k & 1) ? ngroups - 1 - gid : gid);
+    };
+
+    s16x2 Mr[Q], Ir[Q], Dr[Q];
+    int k = 0;                   // this group's k-th record
+    int t = record_of(0);
+    uint4 rec = make_uint4(0u, 0u, 0u, 0u), rec16 = rec;
+    uint32_t lm = 0u;
+    if (t < nseq) {
+        rec = *(const uint4 *)(a.seqs + t);
+        rec16 = *((const uint4 *)(a.seqs + t) + 1);
+        lm = a.lenmodel[t];
+    }
+    // the next record, loaded while the current one runs
+    uint4 nrec = rec, nrec16 = rec16;
+    uint32_t nlm = lm;
+    auto prefetch = [&]() {
+        const int tn = record_of(k + 1);
+        if (tn < nseq) {
+            nrec = *(const uint4 *)(a.seqs + tn);
+            nrec16 = *((const uint4 *)(a.seqs + tn) + 1);
+            nlm = a.lenmodel[tn];
+        }
+    };
+
+    bool active = false;
+    uint32_t off = a.pad_off, seq_off = a.pad_off, id = 0;
+    int len = 0, done = 0;       // residues of the sequence, rows run so far
+    int loop = 0, move = 0;      // length model: N/J/C loops, N/J->B and C->T
+    int xN = 0, xB = 0, xJ = kP7Neg, xC = kP7Neg;
+    bool ovf = false;
+    uint4 wv = make_uint4(0u, 0u, 0u, 0u);   // this step's 16 residues
+    const s16x2 neg = splat16(kP7Neg);
+    auto start = [&]() {
+        active = t < nseq;
+        seq_off = active ? rec.x : a.pad_off;
+        off = seq_off;
+        id = rec.z;
+        len = active ? (int)rec.w : 0;
+        done = 0;
+        loop = (int)(short)(lm & 0xffffu);
+        move = (int)(short)(lm >> 16);
+        xN = 0;
+        xB = sat16(xN + move);
+        xJ = kP7Neg;
+        xC = kP7Neg;
+        ovf = false;
+        wv = active ? rec16 : make_uint4(0x14141414u, 0x14141414u, 0x14141414u, 0x14141414u);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) Mr[q] = Ir[q] = Dr[q] = neg;
+    };
+    start();
+    prefetch();
+
+    for (;;) {
+        if (!__any(active)) break;
+        bool ended = false;
+        do {
+            // residues of the next step (the database stores every sequence
+            // in whole 16-residue steps plus 16 more bytes)
+            const uint4 wn = *(const uint4 *)(a.res + off + 16u);
+#pragma unroll 1
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t word = r < 4 ? wv.x : r < 8 ? wv.y : r < 12 ? wv.z : wv.w;
+                const uint32_t x = (word >> (8 * (r & 3))) & 0xffu;
+                const bool live = active && done + r < len;
+                const s16x2 bc = splat16(sat16(xB + a.tbm));
+                // ---- M, I, and D within each element ----------------------
+                s16x2 gM = as_s16x2(shift_in(s16_bits(Mr[Q - 1])));
+                s16x2 gI = as_s16x2(shift_in(s16_bits(Ir[Q - 1])));
+                s16x2 gD = as_s16x2(shift_in(s16_bits(Dr[Q - 1])));
+                s16x2 xe = neg;
+                uint32_t md0 = 0u;
+                // register q from its dwords of the 8 rows (emission, then
+                // MMp, IMp, DMp, MI, II, MDp, DDp)
+                auto cell = [&](int q, uint32_t e, uint32_t mm, uint32_t im, uint32_t dm,
+                                uint32_t mi, uint32_t ii, uint32_t md, uint32_t dd) {
+                    const s16x2 oM = Mr[q], oI = Ir[q], oD = Dr[q];
+                    const s16x2 c = smax(smax(adds(gM, as_s16x2(mm)), adds(gI, as_s16x2(im))),
+                                         smax(adds(gD, as_s16x2(dm)), bc));
+                    Mr[q] = adds(c, as_s16x2(e));
+                    Ir[q] = smax(adds(oM, as_s16x2(mi)), adds(oI, as_s16x2(ii)));
+                    Dr[q] = q == 0 ? neg
+                                   : smax(adds(Mr[q - 1], as_s16x2(md)),
+                                          adds(Dr[q - 1], as_s16x2(dd)));
+                    if (q == 0) md0 = md;
+                    xe = smax(xe, Mr[q]);
+                    gM = oM;
+                    gI = oI;
+                    gD = oD;
+                };
+#pragma unroll
+                for (int ch = 0; ch < Lay::NF; ++ch) {
+                    // one chunk's 32 score dwords at a time: keeps the
+                    // scheduler from hoisting every chunk's loads at once
+                    __builtin_amdgcn_sched_barrier(0);
+                    const uint4 ve = chunk(x, ch), vmm = chunk(rT + kP7MMp, ch),
+                                vim = chunk(rT + kP7IMp, ch), vdm = chunk(rT + kP7DMp, ch),
+                                vmi = chunk(rT + kP7MI, ch), vii = chunk(rT + kP7II, ch),
+                                vmd = chunk(rT + kP7MDp, ch), vdd = chunk(rT + kP7DDp, ch);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (ch * 4 + u < Q)
+                            cell(ch * 4 + u, comp(ve, u), comp(vmm, u), comp(vim, u),
+                                 comp(vdm, u), comp(vmi, u), comp(vii, u), comp(vmd, u),
+                                 comp(vdd, u));
+                    }
+                }
+                if constexpr (Lay::T2) {
+                    const uint2 ve = tail2(x), vmm = tail2(rT + kP7MMp), vim = tail2(rT + kP7IMp),
+                                vdm = tail2(rT + kP7DMp), vmi = tail2(rT + kP7MI),
+                                vii = tail2(rT + kP7II), vmd = tail2(rT + kP7MDp),
+                                vdd = tail2(rT + kP7DDp);
+                    cell(Lay::Q2, ve.x, vmm.x, vim.x, vdm.x, vmi.x, vii.x, vmd.x, vdd.x);
+                    cell(Lay::Q2 + 1, ve.y, vmm.y, vim.y, vdm.y, vmi.y, vii.y, vmd.y, vdd.y);
+                }
+                if constexpr (Lay::T1) {
+                    cell(Lay::Q1, tail1(x), tail1(rT + kP7MMp), tail1(rT + kP7IMp),
+                         tail1(rT + kP7DMp), tail1(rT + kP7MI), tail1(rT + kP7II),
+                         tail1(rT + kP7MDp), tail1(rT + kP7DDp));
+                }
+                // ---- D chains across elements (lazy F) --------------------
+                // each element's first slot takes the previous element's last
+                // M (through M->D) and last D (through D->D), carried along
+                // its slots, until no element's last D changes
+                const s16x2 cinM = adds(as_s16x2(shift_in(s16_bits(Mr[Q - 1]))), as_s16x2(md0));
+                for (;;) {
+                    const uint32_t last = s16_bits(Dr[Q - 1]);
+                    s16x2 carry = as_s16x2(shift_in(last));
+                    auto link = [&](int q, uint32_t dd) {
+                        const s16x2 c = q == 0 ? smax(cinM, adds(carry, as_s16x2(dd)))
+                                               : adds(Dr[q - 1], as_s16x2(dd));
+                        Dr[q] = smax(Dr[q], c);
+                    };
+#pragma unroll
+                    for (int ch = 0; ch < Lay::NF; ++ch) {
+                        const uint4 vdd = chunk(rT + kP7DDp, ch);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (ch * 4 + u < Q) link(ch * 4 + u, comp(vdd, u));
+                    }
+                    if constexpr (Lay::T2) {
+                        const uint2 vdd = tail2(rT + kP7DDp);
+                        link(Lay::Q2, vdd.x);
+                        link(Lay::Q2 + 1, vdd.y);
+                    }
+                    if constexpr (Lay::T1) link(Lay::Q1, tail1(rT + kP7DDp));
+                    if (!__any(s16_bits(Dr[Q - 1]) != last)) break;
+                }
+                // ---- special states (Plan-7 N, B, E, C, J) ----------------
+                const int eh = (int)xe.x > (int)xe.y ? (int)xe.x : (int)xe.y;
+                const int E = group_max<G>(eh);
+                if (live) {
+                    if (E >= kP7Pos) ovf = true;
+                    const int j1 = sat16(xJ + loop), j2 = sat16(E + kP7Half);
+                    xJ = j1 > j2 ? j1 : j2;
+                    const int c1 = sat16(xC + loop), c2 = sat16(E + kP7Half);
+                    xC = c1 > c2 ? c1 : c2;
+                    xN = sat16(xN + loop);
+                    const int b1 = sat16(xN + move), b2 = sat16(xJ + move);
+                    xB = b1 > b2 ? b1 : b2;
+                }
+            }
+            done += 16;
+            // groups without a sequence stay on the padding (>= 64 bytes of
+            // code 20 at pad_off)
+            if (active) off += 16u;
+            wv = wn;
+            ended = active && done >= len;
+        } while (!__any(ended));
+
+        // ---- finished sequences: score, then the next record ---------------
+        if (ended && gstart) {
+            a.score[id] = ovf ? (int16_t)kP7Pos : (int16_t)sat16(xC + move);
+            a.flag[id] = ovf ? 1 : 0;
+        }
+        if (ended) {
+            ++k;
+            t = record_of(k);
+            rec = nrec;
+            rec16 = nrec16;
+            lm = nlm;
+            start();
+            prefetch();
+        }
+    }
+}
+
+// At most 8 wavefronts per block: with 1024 threads the compiler caps the
+// kernel at 128 VGPRs and spills the cell registers of the wider plans.
+constexpr int kP7MaxWaves = 8;
+
+// The LDS image, then the filter kernel.
+template <int G, int Q>
+hipError_t launch_p7(const P7Args &a, int wpb, int blocks, hipStream_t s) {
+    constexpr int n = kP7Rows * lds_layout(G, Q, kP7Rows).RS;
+    if (wpb < 1 || wpb > kP7MaxWaves) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((p7_prep_kernel<G, Q>), dim3((n + 255) / 256), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = p7_lds_bytes(G, Q);
+    if (lds > 64 * 1024) {
+        e = hipFuncSetAttribute((const void *)p7_kernel<G, Q, 512>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((p7_kernel<G, Q, 512>), dim3(blocks), dim3(wpb * 64), lds, s, a);
+    return hipGetLastError();
+}
+
+// Resident blocks of wpb wavefronts per CU (0 on error).
+template <int G, int Q>
+int occupancy_p7(int wpb) {
+    if (wpb < 1 || wpb > kP7MaxWaves) return 0;
+    int nb = 0;
+    const size_t lds = p7_lds_bytes(G, Q);
+    if (hipFuncSetAttribute((const void *)p7_kernel<G, Q, 512>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, p7_kernel<G, Q, 512>, wpb * 64,
+                                                     lds) != hipSuccess)
+        return 0;
+    return nb;
+}
+
+}  // namespace hmsv
