@@ -14,7 +14,11 @@ entry and exit, or the length model.  The reading implemented here:
   -32768 stands for -inf (probability zero) and is the starting value of
   every cell: ``q(p) = RHAZ(32 * log2(p))`` for p > 0, -32768 for p = 0;
 * match emissions ``msc_k(x) = q(e_k(x) / bg(x))`` (a ratio, not a
-  probability: RHAZ(32 log2 ratio)), -32768 for codes 20..31 and e = 0;
+  probability: RHAZ(32 log2 ratio)), -32768 for e = 0; degenerate codes
+  21..26 (the sets of ``quant.DEGENERATE``) score ``RHAZ(32 * mean)`` of the
+  background-weighted mean of their members' log2 ratios (-32768 if a
+  member has e = 0), as the MSV tables do in third-bits; codes 20 and
+  27..31 score -32768;
   insert states emit with score 0 (inserts follow the background);
 * transitions out of node k: ``tMM, tMI, tMD, tIM, tII, tDM, tDD`` =
   q(probability); node M has no successor and no insert state, so its
@@ -32,7 +36,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .quant import rhaz
+from .quant import DEGENERATE, degenerate_mean_log2, rhaz
 
 UNITS = 32              # score units per bit
 NEG = -32768            # -inf
@@ -57,6 +61,11 @@ def quantize(emis: np.ndarray, trans: np.ndarray, bg: np.ndarray) -> dict:
     M = emis.shape[0]
     msc = np.full((32, M), NEG, dtype=np.int64)
     msc[:20] = q(emis / np.asarray(bg, dtype=np.float64)[None, :]).T
+    for code in DEGENERATE:
+        m = degenerate_mean_log2(emis, bg, code)
+        fin = np.isfinite(m)
+        v = np.clip(rhaz(UNITS * np.where(fin, m, 0.0)), NEG, POS)
+        msc[code] = np.where(fin, v, NEG)
     t = q(trans).T.copy()                       # [7, M]
     t[[0, 2, 3, 5, 6], M - 1] = NEG             # no node M + 1
     t[[1, 4], M - 1] = NEG                      # no insert state at node M

@@ -11,7 +11,16 @@ reading implemented here, with every constant, is:
 * log-odds in third-bits, rounded half away from zero in float64:
   ``r_k(x) = RHAZ(3 * log2(e_k(x) / bg(x)))`` for x < 20, ``-inf`` if e = 0;
 * ``bias = max_{k, x<20} r_k(x)`` (the offset the MSV kernel adds, Alg. 2);
-* unsigned MSV cost ``cost_k(x) = min(255, bias - r_k(x))``, 255 for x >= 20;
+* degenerate codes (the paper's table has 32 entries per node, Alg. 4,
+  Sec. 3.3; it does not say how ambiguous residues score): code 21 B =
+  {D, N}, 22 J = {I, L}, 23 Z = {E, Q}, 24 U = {C}, 25 O = {K}, 26 X = all
+  twenty; each scores the background-weighted mean of its members' log-odds
+  (the expected score of a residue drawn from the background restricted to
+  the set), ``r_k(D) = RHAZ(3 * (sum_x bg(x) log2(e_k(x)/bg(x))) /
+  (sum_x bg(x)))`` summed in ascending code order, ``-inf`` if a member has
+  e = 0; codes 20 and 27..31 never score;
+* unsigned MSV cost ``cost_k(x) = min(255, bias - r_k(x))`` (bias over
+  x < 20 only), 255 for the non-scoring codes and -inf entries;
 * signed SSV score ``sc_k(x) = max(-128, bias - cost_k(x))`` (Alg. 7 keeps
   -inf as 0x80, i.e. -128);
 * special-state costs from the MSV model's transitions (Sec. 2.1, Fig. 1):
@@ -60,9 +69,41 @@ def tjb(L):
 
 NEG_INF = -(1 << 40)   # stands for -inf in integer log-odds
 
+ALPHABET = "ACDEFGHIKLMNPQRSTVWY"
+# degenerate code -> member residue codes (ascending)
+DEGENERATE = {
+    21: tuple(sorted(ALPHABET.index(c) for c in "DN")),    # B
+    22: tuple(sorted(ALPHABET.index(c) for c in "IL")),    # J
+    23: tuple(sorted(ALPHABET.index(c) for c in "EQ")),    # Z
+    24: (ALPHABET.index("C"),),                             # U
+    25: (ALPHABET.index("K"),),                             # O
+    26: tuple(range(K)),                                    # X
+}
+DEGENERATE_LETTERS = {"B": 21, "J": 22, "Z": 23, "U": 24, "O": 25, "X": 26}
+
+
+def degenerate_mean_log2(emis: np.ndarray, bg: np.ndarray, code: int):
+    """sum_x bg(x) log2(e_k(x)/bg(x)) / sum_x bg(x) over the members of a
+    degenerate code, one float64 per node, summed member by member in
+    ascending code order; -inf where a member's emission is 0."""
+    emis = np.asarray(emis, dtype=np.float64)
+    bg = np.asarray(bg, dtype=np.float64)
+    M = emis.shape[0]
+    num = np.zeros(M, dtype=np.float64)
+    den = 0.0
+    dead = np.zeros(M, dtype=bool)
+    for x in DEGENERATE[code]:
+        ratio = emis[:, x] / bg[x]
+        dead |= ~(ratio > 0)
+        with np.errstate(divide="ignore"):
+            num = num + bg[x] * np.log2(np.where(ratio > 0, ratio, 1.0))
+        den = den + bg[x]
+    return np.where(dead, -np.inf, num / den)
+
 
 def log_odds(emis: np.ndarray, bg: np.ndarray) -> np.ndarray:
-    """r[x, k] for x in 0..31 (int64, NEG_INF for zero emissions / x >= 20)."""
+    """r[x, k] for x in 0..31 (int64; NEG_INF for zero emissions and the
+    non-scoring codes 20, 27..31)."""
     emis = np.asarray(emis, dtype=np.float64)
     M = emis.shape[0]
     r = np.full((KP, M), NEG_INF, dtype=np.int64)
@@ -71,6 +112,10 @@ def log_odds(emis: np.ndarray, bg: np.ndarray) -> np.ndarray:
     with np.errstate(divide="ignore"):
         vals = rhaz(3.0 * np.log2(np.where(pos, ratio, 1.0)))
     r[:K] = np.where(pos, vals, NEG_INF)
+    for code in DEGENERATE:
+        m = degenerate_mean_log2(emis, bg, code)
+        fin = np.isfinite(m)
+        r[code] = np.where(fin, rhaz(3.0 * np.where(fin, m, 0.0)), NEG_INF)
     return r
 
 
@@ -81,6 +126,8 @@ def quantize(emis: np.ndarray, bg: np.ndarray):
     bias = int(r[:K].max())
     cost = np.full((KP, M), 255, dtype=np.int64)
     cost[:K] = np.minimum(255, bias - r[:K])
+    for code in DEGENERATE:
+        cost[code] = np.minimum(255, bias - r[code])
     sc = np.maximum(-128, bias - cost)
     return {"cost": cost.astype(np.uint8), "sc": sc.astype(np.int8), "bias": bias,
             "M": M, "tbm": tbm(M), "r": r}
@@ -89,12 +136,14 @@ def quantize(emis: np.ndarray, bg: np.ndarray):
 def from_costs(cost: np.ndarray, bias: int):
     """A profile given directly by its 8-bit MSV cost table [32, M] and
     offset ``bias`` (no emissions): the SSV table is derived as above,
-    ``sc = max(-128, bias - cost)``, and codes 20..31 cost 255 (-inf)
-    whatever the given rows 20..31 hold.  Same dict as ``quantize``."""
+    ``sc = max(-128, bias - cost)``; the degenerate codes 21..26 score
+    with the given rows, and codes 20 and 27..31 cost 255 (-inf) whatever
+    their rows hold.  Same dict as ``quantize``."""
     c = np.array(cost, dtype=np.int64)
     if c.ndim != 2 or c.shape[0] != KP:
         raise ValueError("cost must be [32, M]")
-    c[K:] = 255
+    c[K] = 255
+    c[27:] = 255
     M = c.shape[1]
     sc = np.maximum(-128, int(bias) - c)
     return {"cost": c.astype(np.uint8), "sc": sc.astype(np.int8), "bias": int(bias),

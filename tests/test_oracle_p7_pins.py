@@ -29,7 +29,10 @@ def test_quantizer_constants():
     prof = p7.quantize(np.full((3, 20), 0.05), synth.sample_transitions(
         np.random.default_rng(0), 3), np.full(20, 0.05))
     assert prof["tbm"] == -83                   # 2 / (3 * 4) = 1/6
-    assert (prof["msc"][:20] == 0).all() and (prof["msc"][20:] == NEG).all()
+    # e = bg: every residue and every degenerate code (21..26) scores 0;
+    # the non-scoring codes 20 and 27..31 are -inf
+    assert (prof["msc"][:20] == 0).all() and (prof["msc"][21:27] == 0).all()
+    assert (prof["msc"][20] == NEG).all() and (prof["msc"][27:] == NEG).all()
     # node M has no successor and no insert state
     assert (prof["trans"][:, 2] == NEG).all()
 

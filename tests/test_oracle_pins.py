@@ -71,7 +71,12 @@ def test_quantizer_powers_of_two_fixture():
     assert cost[0, 2] == 0 and cost[11, 2] == 6
     assert set(np.delete(cost[:20, 2], [0, 11])) == {255}
     assert set(np.delete(sc[:20, 2], [0, 11])) == {-128}
-    assert (cost[20:] == 255).all() and (sc[20:] == -128).all()
+    # degenerate codes 21..26 (B, J, Z, U, O, X): the mean of the members'
+    # exponents (uniform bg), times 3, rounded half away from zero
+    assert list(cost[21:27, 0]) == [14, 18, 14, 6, 18, 16]
+    assert (cost[21:27, 1] == 12).all() and (cost[21:27, 2] == 255).all()
+    for c in (20, 27, 28, 29, 30, 31):
+        assert (cost[c] == 255).all() and (sc[c] == -128).all()
     assert (sc[:20, :2] == 12 - cost[:20, :2]).all()
 
 
@@ -120,12 +125,14 @@ def test_hand_worked_examples(case):
     name, prof, x, msv_exp, ssv_exp = case
     assert oracle.msv_seq(prof, x) == msv_exp
     assert oracle.ssv_seq(prof, x) == ssv_exp
-    # the same profile built from its cost table alone (rows 20..31 given
-    # as anything) scores the same
+    # the same profile built from its cost table alone (the non-scoring
+    # rows 20 and 27..31 given as anything) scores the same
     cost = prof["cost"].copy()
-    cost[20:] = 7
+    cost[20] = 7
+    cost[27:] = 7
     p2 = q.from_costs(cost, prof["bias"])
-    assert (p2["sc"] == prof["sc"]).all() and (p2["cost"][20:] == 255).all()
+    assert (p2["sc"] == prof["sc"]).all() and (p2["cost"][20] == 255).all()
+    assert (p2["cost"][27:] == 255).all()
     assert oracle.msv_seq(p2, x) == msv_exp
     assert oracle.ssv_seq(p2, x) == ssv_exp
 
