@@ -40,10 +40,21 @@ const char *hmsv_strerror(hmsv_status s);
 
 /* ---- model constants (MSV model of paper Sec. 2.1, Fig. 1) ------------- */
 #define HMSV_K        20    /* scoring amino acids, codes 0..19 (ACDEFGHIKLMNPQRSTVWY) */
-#define HMSV_KP       32    /* table rows: codes 20..31 are non-scoring (Alg. 4's 32-entry table) */
+#define HMSV_KP       32    /* table rows per node (Alg. 4's 32-entry table) */
+/* Residue codes: 0..19 the amino acids ACDEFGHIKLMNPQRSTVWY; 21..26 the
+ * degenerate codes B = {D, N}, J = {I, L}, Z = {E, Q}, U = {C}, O = {K},
+ * X = any of the twenty; 20 and 27..31 are non-scoring (-inf).  The paper's
+ * table has 32 entries per node but does not say how ambiguous residues
+ * score: here a degenerate code scores the background-weighted mean of its
+ * members' log2 odds ratios (the expected score of a residue drawn from the
+ * background restricted to the set). */
+#define HMSV_DEGEN_FIRST 21
+#define HMSV_DEGEN_LAST  26
 #define HMSV_BASE    190    /* N/J level of the MSV special states */
 #define HMSV_TEC       3    /* E->J and E->C cost, -round(3 log2 1/2) */
-#define HMSV_MAX_M  3839    /* longest profile: its LDS table (21 rows x 3840 fp16) fits 160 KiB */
+#define HMSV_MAX_M  3839    /* longest profile: its LDS table (21 rows x 3840 fp16) fits 160 KiB;
+                               a database with degenerate codes needs 27 rows (M up to 2559
+                               with 64-lane groups; HMSV_EUNSUPPORTED beyond) */
 #define HMSV_MAX_BIAS 64    /* dbias bound under which the kernels may omit the 255 cap */
 
 /* Uniform local-entry cost of a length-M profile: -round(3 log2(2/(M(M+1)))),
@@ -84,8 +95,12 @@ hmsv_status hmsv_gumbel_pvalue(const double *nats, int64_t n, double mu, double 
  * Turns per-node match emission probabilities into the 8-bit tables of the
  * MSV (Alg. 2 sigma/dbias) and SSV (Alg. 7) kernels:
  *   r_k(x)    = round(3 log2(emis[k][x] / bg[x])) for x < 20 (-inf if emis = 0)
- *   dbias     = max_{k,x} r_k(x)
- *   cost[x][k]= min(255, dbias - r_k(x)) for x < 20, 255 for x >= 20
+ *   r_k(D)    = round(3 m), m = sum_x bg[x] log2(emis[k][x] / bg[x]) / sum_x bg[x]
+ *               over the members x of degenerate code D (21..26), summed in
+ *               ascending code order (-inf if a member's emis = 0)
+ *   dbias     = max_{k,x<20} r_k(x)
+ *   cost[x][k]= min(255, dbias - r_k(x)) for x < 20 and x in 21..26 (255
+ *               for -inf), 255 for x = 20 and x >= 27
  *   sc[x][k]  = max(-128, dbias - cost[x][k])
  * emis: host, [M][20] float64, row k = node k+1, columns in code order.
  * bg:   host, [20] float64 background frequencies, all > 0.
@@ -98,10 +113,11 @@ hmsv_status hmsv_quantize(const double *emis, const double *bg, int32_t M,
 /* ---- profile ------------------------------------------------------------
  * A quantized profile whose tables live in caller-owned device memory.
  * cost (MSV) and sc (SSV) are [32][M] residue-major, as hmsv_quantize writes
- * them.  Only rows 0..19 are read: codes 20..31 (and the kernels' padding
+ * them.  Rows 0..19 and 21..26 are read (21..26 only for databases that
+ * hold degenerate codes); codes 20 and 27..31 (and the kernels' padding
  * rows) always score as -inf, i.e. cost 255 and sc -128, whatever the
- * caller's rows 20..31 hold (hmsv_quantize writes exactly those values
- * there).  The library only reads the tables.  Either table may be NULL if
+ * caller's rows 20 and 27..31 hold (hmsv_quantize writes exactly those
+ * values there).  The library only reads the tables.  Either table may be NULL if
  * that filter is not used.  Preconditions checked on the host:
  * 1 <= M <= HMSV_MAX_M and 0 <= dbias <= HMSV_MAX_BIAS.  MSV reads only
  * cost (and dbias), SSV only sc. */
@@ -132,6 +148,10 @@ void hmsv_db_destroy(hmsv_db *db);
 int64_t hmsv_db_nseq(const hmsv_db *db);
 int64_t hmsv_db_residues(const hmsv_db *db);     /* real residues (no padding) */
 int64_t hmsv_db_padded_rows(const hmsv_db *db);  /* rows the kernels run */
+/* Table rows the database's scoring calls put in LDS: 27 if it holds a
+ * degenerate code (21..26), else 21 (-1 for NULL).  hmsv_db_create keeps
+ * codes 0..19 and 21..26 and stores every other code as 20. */
+int32_t hmsv_db_table_rows(const hmsv_db *db);
 
 /* ---- launch plan --------------------------------------------------------
  * How one filter call maps onto the GPU.  A lane group of G lanes (a power
@@ -164,8 +184,16 @@ hmsv_status hmsv_default_plan(int32_t is_msv, int32_t M, hmsv_plan *plan);
  * the kernel's layout, the same for both filters), or 0 if G is not a power
  * of two in 1..64 or Q < 1.  Plans above 160 KiB are rejected by the
  * scoring calls (HMSV_EUNSUPPORTED); a scheduler can add the figures of
- * kernels it wants to co-reside on one CU. */
+ * kernels it wants to co-reside on one CU.  This is the 21-row image; on a
+ * database that holds degenerate codes it has 27 rows (x 27 / 21). */
 size_t hmsv_plan_lds_bytes(int32_t G, int32_t Q);
+
+/* The plan a call with plan = NULL uses on this database: hmsv_default_plan,
+ * or, when the database holds degenerate codes and that plan's 27-row image
+ * does not fit the LDS, the narrowest lane group whose image does (LDS
+ * bytes are then hmsv_plan_lds_bytes x 27 / 21).  HMSV_EUNSUPPORTED if none
+ * does (or, for MSV, if the exact pass's 64-lane image does not). */
+hmsv_status hmsv_db_default_plan(const hmsv_db *db, int32_t is_msv, int32_t M, hmsv_plan *plan);
 
 /* Device workspace needed by a scoring call on a database of nseq
  * sequences (bytes; pass the database's full sequence count, also for
@@ -303,12 +331,14 @@ void hmsv_batch_destroy(hmsv_batch *batch);
  * B = move, all else -inf.  Score = C[L] + move, or 32767 with flags = 1
  * once a row's E saturates at 32767. */
 #define HMSV_P7_UNITS 32
-#define HMSV_P7_MAX_M 2815  /* 64-lane groups of 22 registers: 28 table rows fill 160 KiB */
+#define HMSV_P7_MAX_M 2815  /* 64-lane groups of 22 registers: 28 table rows fill 160 KiB
+                               (34 rows with degenerate codes: M up to 2047) */
 
 /* Emissions [M][20] (as hmsv_quantize), transitions [M][7] float64
  * probabilities out of each node in the order M->M, M->I, M->D, I->M,
  * I->I, D->M, D->D, background [20] -> msc [32][M] int16 =
- * round(32 log2(emis / bg)) (-32768 for zero emissions and codes 20..31),
+ * round(32 log2(emis / bg)) (-32768 for zero emissions and codes 20, 27..31;
+ * degenerate codes 21..26 score round(32 m) with m as in hmsv_quantize),
  * trans_out [7][M] int16 = round(32 log2 p) (-32768 for p = 0, and for
  * every transition of node M, which has no successor and no insert state),
  * tbm = round(32 log2(2 / (M (M + 1)))), all rounded half away from zero

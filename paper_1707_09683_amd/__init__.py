@@ -77,6 +77,10 @@ _lib.hmsv_db_destroy.argtypes = [_P]
 for _f in ("hmsv_db_nseq", "hmsv_db_residues", "hmsv_db_padded_rows"):
     getattr(_lib, _f).restype = _i64
     getattr(_lib, _f).argtypes = [_P]
+_lib.hmsv_db_table_rows.restype = _i32
+_lib.hmsv_db_table_rows.argtypes = [_P]
+_lib.hmsv_db_default_plan.restype = ctypes.c_int
+_lib.hmsv_db_default_plan.argtypes = [_P, _i32, _i32, ctypes.POINTER(Plan)]
 _lib.hmsv_default_plan.restype = ctypes.c_int
 _lib.hmsv_default_plan.argtypes = [_i32, _i32, ctypes.POINTER(Plan)]
 _lib.hmsv_workspace_bytes.restype = ctypes.c_size_t
@@ -127,7 +131,8 @@ EXPORTED = ("hmsv_strerror", "hmsv_tbm", "hmsv_tjb", "hmsv_quantize", "hmsv_db_c
             "hmsv_batch_create", "hmsv_batch_launch", "hmsv_batch_destroy",
             "hmsv_msv_score_range", "hmsv_ssv_score_range", "hmsv_db_order",
             "hmsv_split_info", "hmsv_score_nats", "hmsv_gumbel_pvalue",
-            "hmsv_msv_score_noalloc", "hmsv_p7_quantize", "hmsv_p7_length_model",
+            "hmsv_msv_score_noalloc", "hmsv_db_table_rows", "hmsv_db_default_plan",
+            "hmsv_p7_quantize", "hmsv_p7_length_model",
             "hmsv_p7_lds_bytes", "hmsv_p7_default_plan", "hmsv_p7_score")
 
 
@@ -204,6 +209,8 @@ class Database:
         self.nseq = int(_lib.hmsv_db_nseq(h))
         self.residues = int(_lib.hmsv_db_residues(h))
         self.padded_rows = int(_lib.hmsv_db_padded_rows(h))
+        # LDS table rows of its scoring calls: 27 with degenerate codes, else 21
+        self.table_rows = int(_lib.hmsv_db_table_rows(h))
 
     def order(self) -> np.ndarray:
         """Processing order: original index of each position (longest first)."""
@@ -227,6 +234,15 @@ def default_plan(filt: str, M: int) -> Plan:
     p = Plan()
     _check(_lib.hmsv_default_plan(1 if filt == "msv" else 0, int(M), ctypes.byref(p)),
            "hmsv_default_plan")
+    return p
+
+
+def db_default_plan(db, filt: str, M: int) -> Plan:
+    """The plan a call with plan=None uses on this database (the default
+    plan, or one whose image fits the LDS with the degenerate rows)."""
+    p = Plan()
+    _check(_lib.hmsv_db_default_plan(db._h, 1 if filt == "msv" else 0, int(M), ctypes.byref(p)),
+           "hmsv_db_default_plan")
     return p
 
 
@@ -277,7 +293,7 @@ def _score(filt, profile: Profile, db: Database, score, flags, workspace, plan, 
     if stream is None:
         stream = torch.cuda.current_stream(dev)
     if plan is None:
-        plan = plan_for(filt, profile.M)
+        plan = db_default_plan(db, filt, profile.M)
     pl = ctypes.byref(plan) if plan is not None else None
     with torch.cuda.device(dev):
         if rng is None:

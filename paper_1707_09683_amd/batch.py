@@ -12,7 +12,7 @@ import ctypes
 import torch
 
 from . import (_CProfile, Plan, Profile, Database, _lib, _check, workspace_bytes,
-               plan_for)
+               db_default_plan)
 
 
 class _CQuery(ctypes.Structure):
@@ -55,7 +55,8 @@ class Batch:
             s = torch.empty(n, dtype=sdt, device=dev)
             f = torch.empty(n, dtype=torch.uint8, device=dev)
             ws = torch.zeros(workspace_bytes(n), dtype=torch.uint8, device=dev)
-            p = plans[i] if plans is not None and plans[i] is not None else plan_for(filt, prof.M)
+            p = plans[i] if plans is not None and plans[i] is not None \
+                else db_default_plan(db, filt, prof.M)
             self.scores.append(s)
             self.flags.append(f)
             self.workspaces.append(ws)

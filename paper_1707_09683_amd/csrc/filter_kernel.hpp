@@ -302,7 +302,7 @@ filter_kernel(KArgs a) {
     {
         const uint4 *src = (const uint4 *)a.image;
         uint4 *dst = (uint4 *)lds;
-        constexpr int n16 = kRows * RS / 4;
+        const int n16 = a.rows * (RS / 4);
         for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
     }
     __syncthreads();
@@ -759,13 +759,13 @@ __device__ __forceinline__ uint32_t image_dword(const KArgs &a, const LdsLayout 
 
 // Per call: the filter kernel's LDS image of the profile and, for MSV, the
 // exact pass's image (Layout<64, qx>); threads 0..3 reset the counters.
-// For MSV, kRows more blocks compute best[x] = max_k (dbias - cost_k(x)).
+// For MSV, a.rows more blocks compute best[x] = max_k (dbias - cost_k(x)).
 // The last blocks build the records and slots of split sequences.
 template <int G, int Q, bool MSV>
 __global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks, int ximage_blocks) {
     constexpr LdsLayout D = lds_layout(G, Q);
     const int best_block0 = image_blocks + ximage_blocks;
-    const int seg_block0 = best_block0 + (MSV ? kRows : 0);
+    const int seg_block0 = best_block0 + (MSV ? a.rows : 0);
     const int b = (int)blockIdx.x;
     if (b >= seg_block0) {
         int t = (b - seg_block0) * 256 + (int)threadIdx.x;
@@ -795,12 +795,12 @@ __global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks, in
         // MSV: the exact pass's image
         const LdsLayout X = lds_layout(kExactG, a.qx);
         const int idx = (b - image_blocks) * 256 + (int)threadIdx.x;
-        if (idx < kRows * X.RS) a.ximage[idx] = image_dword<true>(a, X, kExactG, a.qx, idx);
+        if (idx < a.rows * X.RS) a.ximage[idx] = image_dword<true>(a, X, kExactG, a.qx, idx);
         return;
     }
     const int idx = b * 256 + (int)threadIdx.x;
     if (idx < 4) a.counter[idx] = 0u;
-    if (idx < kRows * D.RS) a.image[idx] = image_dword<MSV>(a, D, G, Q, idx);
+    if (idx < a.rows * D.RS) a.image[idx] = image_dword<MSV>(a, D, G, Q, idx);
 }
 
 // MSV exact pass over the windows the filter kernel stored (Alg. 2 with
@@ -852,7 +852,7 @@ __global__ void __launch_bounds__(THREADS) exact_kernel(KArgs a) {
     {
         const uint4 *src = (const uint4 *)a.ximage;
         uint4 *dst = (uint4 *)lds;
-        constexpr int n16 = kRows * RS / 4;
+        const int n16 = a.rows * (RS / 4);
         for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
     }
     __syncthreads();
@@ -1001,7 +1001,7 @@ constexpr int kMaxWaves = G >= 32 ? 16 : 8;
 
 template <int G, int Q, int MODE, int THREADS>
 hipError_t launch_filter_kernel(const KArgs &a, int wpb, int blocks, hipStream_t s) {
-    size_t lds = lds_bytes(G, Q);
+    size_t lds = lds_bytes(G, Q, a.rows);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)filter_kernel<G, Q, MODE, THREADS>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1025,12 +1025,13 @@ hipError_t launch_filter_mode(const KArgs &a, int wpb, int blocks, hipStream_t s
 // MSV with scB fixed (the host launches the exact pass next).
 template <int G, int Q, bool MSV>
 hipError_t launch_filter(const KArgs &a, int wpb, int blocks, hipStream_t s) {
-    constexpr int n = kRows * Layout<G, Q>::RS;
-    constexpr int nb = (n + 255) / 256;
+    if (a.rows != kRows && a.rows != kDegenRows) return hipErrorInvalidValue;
+    const int n = a.rows * Layout<G, Q>::RS;
+    const int nb = (n + 255) / 256;
     if (wpb < 1 || wpb > kMaxWaves<G>) return hipErrorInvalidValue;
-    const int xb = MSV ? (kRows * lds_layout(kExactG, a.qx).RS + 255) / 256 : 0;
+    const int xb = MSV ? (a.rows * lds_layout(kExactG, a.qx).RS + 255) / 256 : 0;
     const int seg_blocks = (a.nsplit + 255) / 256;
-    hipLaunchKernelGGL((prep_kernel<G, Q, MSV>), dim3(nb + xb + (MSV ? kRows : 0) + seg_blocks),
+    hipLaunchKernelGGL((prep_kernel<G, Q, MSV>), dim3(nb + xb + (MSV ? a.rows : 0) + seg_blocks),
                        dim3(256), 0, s, a, nb, xb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1042,9 +1043,9 @@ hipError_t launch_filter(const KArgs &a, int wpb, int blocks, hipStream_t s) {
 }
 
 template <int G, int Q, int MODE, int THREADS>
-int occupancy_kernel(int wpb) {
+int occupancy_kernel(int wpb, int rows) {
     int nb = 0;
-    size_t lds = lds_bytes(G, Q);
+    size_t lds = lds_bytes(G, Q, rows);
     if (hipFuncSetAttribute((const void *)filter_kernel<G, Q, MODE, THREADS>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
@@ -1055,13 +1056,13 @@ int occupancy_kernel(int wpb) {
 }
 
 template <int G, int Q, bool MSV>
-int occupancy_filter(int wpb) {
+int occupancy_filter(int wpb, int rows) {
     constexpr int MODE = MSV ? kMSV : kSSV;
     if (wpb < 1 || wpb > kMaxWaves<G>) return 0;
     if constexpr (kMaxWaves<G> > 8) {
-        if (wpb > 8) return occupancy_kernel<G, Q, MODE, 1024>(wpb);
+        if (wpb > 8) return occupancy_kernel<G, Q, MODE, 1024>(wpb, rows);
     }
-    return occupancy_kernel<G, Q, MODE, 512>(wpb);
+    return occupancy_kernel<G, Q, MODE, 512>(wpb, rows);
 }
 
 // The exact pass: blocks of four wavefronts, as many as fit on the device
@@ -1070,7 +1071,7 @@ constexpr int kExactThreads = 256;
 
 template <int QX>
 hipError_t launch_exact(const KArgs &a, int cus, hipStream_t s) {
-    const size_t lds = lds_bytes(kExactG, QX);
+    const size_t lds = lds_bytes(kExactG, QX, a.rows);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)exact_kernel<QX, kExactThreads>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

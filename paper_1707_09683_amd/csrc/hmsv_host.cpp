@@ -31,6 +31,8 @@ struct hmsv_db {
     SeqRec *d_seqs = nullptr;
     uint32_t *d_p7len = nullptr;   // per record: P7 length model, loop | move << 16
     uint32_t pad_off = 0;
+    int32_t table_rows = kRows;    // table rows its scoring calls need (kDegenRows
+                                   // if it holds degenerate codes 21..26)
     int device = 0;
     std::vector<int64_t> order;   // processing order -> original index
     std::vector<int64_t> cum_rows; // rows run by records [0, t), t = 0..nseq
@@ -50,6 +52,47 @@ int32_t third_bit_cost(double p) { return (int32_t)(-rhaz(3.0 * std::log2(p))); 
 
 // P7Viterbi score of a probability (or odds ratio) p: round(32 log2 p),
 // clamped to int16; -32768 (-inf) for p = 0.
+// Degenerate residue codes and their member residues (codes of
+// ACDEFGHIKLMNPQRSTVWY, ascending): B = {D, N}, J = {I, L}, Z = {E, Q},
+// U = {C}, O = {K}, X = any.  A degenerate code scores the
+// background-weighted mean of its members' log2 odds ratios.
+struct Degenerate {
+    int code;
+    int n;
+    int member[HMSV_K];
+};
+constexpr Degenerate kDegenerate[] = {
+    {21, 2, {2, 11}},
+    {22, 2, {7, 9}},
+    {23, 2, {3, 13}},
+    {24, 1, {1}},
+    {25, 1, {8}},
+    {26, 20, {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19}},
+};
+
+// sum_x bg(x) log2(e(x) / bg(x)) / sum_x bg(x) over the members (summed in
+// ascending code order, one rounding per operation); false if a member's
+// emission is 0 (the score is then -inf).
+bool degenerate_mean(const double *e, const double *bg, const Degenerate &d, double *mean) {
+    double num = 0.0, den = 0.0;
+    for (int t = 0; t < d.n; ++t) {
+        const int x = d.member[t];
+        const double ratio = e[x] / bg[x];
+        if (!(ratio > 0.0)) return false;
+        const double term = bg[x] * std::log2(ratio);
+        num = num + term;
+        den = den + bg[x];
+    }
+    *mean = num / den;
+    return true;
+}
+
+// Packed code of an input code: residues and degenerate codes stay, every
+// other code (20, 27..31) becomes the non-scoring code 20.
+uint8_t keep_code(uint8_t c) {
+    return c < HMSV_K || (c >= 21 && c <= 26) ? c : kInvalidCode;
+}
+
 constexpr int kP7Units = 32;
 int32_t p7_score(double p) {
     if (!(p > 0.0)) return -32768;
@@ -98,7 +141,7 @@ constexpr int kNumTuned = (int)(sizeof(kTuned) / sizeof(kTuned[0]));
 // Persistent-grid size per (kernel, waves_per_block), measured once per
 // device.  A fixed table (no allocation on the scoring path); when it is
 // full the figure is measured again at each call.
-struct OccEntry { const KernelEntry *e; int wpb; int dev; int blocks; };
+struct OccEntry { const KernelEntry *e; int wpb; int rows; int dev; int blocks; };
 constexpr int kOccCap = 4096;
 std::mutex g_occ_mu;
 OccEntry g_occ[kOccCap];
@@ -124,22 +167,23 @@ int device_cus() {
     return n;
 }
 
-int resident_blocks(const KernelEntry *e, int wpb) {
+int resident_blocks(const KernelEntry *e, int wpb, int rows) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     {
         std::lock_guard<std::mutex> lk(g_occ_mu);
         for (int i = 0; i < g_nocc; ++i)
-            if (g_occ[i].e == e && g_occ[i].wpb == wpb && g_occ[i].dev == dev)
+            if (g_occ[i].e == e && g_occ[i].wpb == wpb && g_occ[i].rows == rows &&
+                g_occ[i].dev == dev)
                 return g_occ[i].blocks;
     }
-    int per_cu = e->occupancy(wpb);
+    int per_cu = e->occupancy(wpb, rows);
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     int blocks = per_cu * cus;
     std::lock_guard<std::mutex> lk(g_occ_mu);
-    if (g_nocc < kOccCap) g_occ[g_nocc++] = OccEntry{e, wpb, dev, blocks};
+    if (g_nocc < kOccCap) g_occ[g_nocc++] = OccEntry{e, wpb, rows, dev, blocks};
     return blocks;
 }
 
@@ -153,24 +197,51 @@ hmsv_status check_profile(const hmsv_profile *p, int is_msv) {
     return HMSV_OK;
 }
 
-hmsv_status check_plan(const hmsv_plan *pl, int M) {
+hmsv_status check_plan(const hmsv_plan *pl, int M, int rows = kRows) {
     if (pl->G < 1 || pl->G > 64 || (64 % pl->G) != 0) return HMSV_EINVAL;
     if (pl->Q < 1) return HMSV_EINVAL;
     if (plan_nodes(pl->G, pl->Q) < M) return HMSV_EINVAL;
     if (pl->waves_per_block < 1 || pl->waves_per_block > (pl->G >= 32 ? 16 : 8))
         return HMSV_EINVAL;
     if (pl->blocks < 0) return HMSV_EINVAL;
-    if (lds_bytes(pl->G, pl->Q) > (size_t)kLdsBytes) return HMSV_EUNSUPPORTED;
+    if (lds_bytes(pl->G, pl->Q, rows) > (size_t)kLdsBytes) return HMSV_EUNSUPPORTED;
     return HMSV_OK;
+}
+
+// The plan of a call on a database whose images need `rows` table rows:
+// the caller's, or the default; if the default's image does not fit the
+// LDS with the degenerate rows, the narrowest lane group whose image does.
+// MSV also needs the exact pass's image (64-lane groups) to fit.
+hmsv_status resolve_plan(int is_msv, int M, int rows, const hmsv_plan *in, hmsv_plan *out) {
+    if (is_msv && lds_bytes(kExactG, exact_q(M), rows) > (size_t)kLdsBytes)
+        return HMSV_EUNSUPPORTED;
+    if (in) {
+        *out = *in;
+        return check_plan(out, M, rows);
+    }
+    hmsv_status st = hmsv_default_plan(is_msv, M, out);
+    if (st != HMSV_OK) return st;
+    if (lds_bytes(out->G, out->Q, rows) <= (size_t)kLdsBytes) return check_plan(out, M, rows);
+    for (int G : {1, 2, 4, 8, 16, 32, 64}) {
+        const int Q = (M + 1 + 2 * G - 1) / (2 * G);
+        if (Q > 32 || lds_bytes(G, Q, rows) > (size_t)kLdsBytes) continue;
+        if (!registry().find(is_msv ? 1 : 0, G, Q)) continue;
+        out->G = G;
+        out->Q = Q;
+        out->waves_per_block = lds_bytes(G, Q, rows) > 48 * 1024 ? 8 : 4;
+        out->blocks = 0;
+        return check_plan(out, M, rows);
+    }
+    return HMSV_EUNSUPPORTED;
 }
 
 // Blocks of a call's launch: the plan's, or a persistent grid of the
 // resident maximum with no more wavefronts than there are lane groups'
 // worth of sequences.  0 on a device error.
-int grid_blocks(const KernelEntry *e, const hmsv_plan &plan, int64_t count) {
+int grid_blocks(const KernelEntry *e, const hmsv_plan &plan, int64_t count, int rows) {
     int blocks = plan.blocks;
     if (blocks == 0) {
-        blocks = resident_blocks(e, plan.waves_per_block);
+        blocks = resident_blocks(e, plan.waves_per_block, rows);
         if (blocks <= 0) return 0;
         int64_t groups_per_block = (int64_t)plan.waves_per_block * (64 / plan.G);
         int64_t need = (count + groups_per_block - 1) / groups_per_block;
@@ -233,14 +304,13 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
     hmsv_status st = check_profile(prof, is_msv);
     if (st != HMSV_OK) return st;
     if (!db || !score || !flags || !workspace) return HMSV_EINVAL;
-    hmsv_plan plan;
     if (plan_in) {
-        plan = *plan_in;
-    } else {
-        st = hmsv_default_plan(is_msv, prof->M, &plan);
+        // the plan's shape first, without the database
+        st = check_plan(plan_in, prof->M);
         if (st != HMSV_OK) return st;
     }
-    st = check_plan(&plan, prof->M);
+    hmsv_plan plan;
+    st = resolve_plan(is_msv, prof->M, db->table_rows, plan_in, &plan);
     if (st != HMSV_OK) return st;
     const KernelEntry *e = registry().find(is_msv, plan.G, plan.Q);
     if (!e) return HMSV_ENOKERNEL;
@@ -269,9 +339,10 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
     a.ximage = (uint32_t *)((char *)workspace + kWsXImageOff);
     a.win = (uint4 *)((char *)workspace + kWsWinOff);
     a.qx = exact_q(prof->M);
+    a.rows = db->table_rows;
     if (((uintptr_t)workspace & 255u) != 0) return HMSV_EINVAL;
 
-    const int blocks = grid_blocks(e, plan, count);
+    const int blocks = grid_blocks(e, plan, count, db->table_rows);
     if (blocks <= 0) return HMSV_EDEVICE;
     plan_split(db, first, count, (int64_t)blocks * plan.waves_per_block * (64 / plan.G),
                prof->M, a);
@@ -423,6 +494,16 @@ hmsv_status hmsv_quantize(const double *emis, const double *bg, int32_t M, uint8
             sc[(size_t)x * M + k] = (int8_t)std::max<int64_t>(-128, best - c);
         }
     }
+    for (const Degenerate &d : kDegenerate) {
+        for (int k = 0; k < M; ++k) {
+            double mean = 0.0;
+            int64_t c = 255;
+            if (degenerate_mean(emis + (size_t)k * HMSV_K, bg, d, &mean))
+                c = std::min<int64_t>(255, best - (int64_t)rhaz(3.0 * mean));
+            cost[(size_t)d.code * M + k] = (uint8_t)c;
+            sc[(size_t)d.code * M + k] = (int8_t)std::max<int64_t>(-128, best - c);
+        }
+    }
     *dbias = (int32_t)best;
     return HMSV_OK;
 }
@@ -440,10 +521,13 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
         if (len[i] < 0) return HMSV_EINVAL;
         residues += len[i];
     }
+    bool degenerate = false;
     for (int64_t i = 0; i < nseq; ++i) {
         const uint8_t *p = res + offsets[i];
-        for (int64_t t = 0; t < len[i]; ++t)
+        for (int64_t t = 0; t < len[i]; ++t) {
             if (p[t] >= HMSV_KP) return HMSV_EINVAL;
+            degenerate = degenerate || (p[t] >= 21 && p[t] <= 26);
+        }
     }
     // Longest first: the dynamic queue then ends with short sequences.
     std::vector<int64_t> order((size_t)nseq);
@@ -477,7 +561,7 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
         int64_t i = order[t];
         const uint8_t *p = res + offsets[i];
         uint8_t *d = packed.data() + recs[t].off;
-        for (int64_t k = 0; k < len[i]; ++k) d[k] = p[k] < HMSV_K ? p[k] : kInvalidCode;
+        for (int64_t k = 0; k < len[i]; ++k) d[k] = keep_code(p[k]);
         recs[t].len = (uint32_t)len[i];
         std::memcpy(recs[t].first16, d, 4 * sizeof(uint32_t));
     }
@@ -487,6 +571,7 @@ hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t n
     db->residues = residues;
     db->rows = (int64_t)rows;
     db->pad_off = pad_off;
+    db->table_rows = degenerate ? kDegenRows : kRows;
     try {
         db->order = order;
         db->cum_rows = cum_rows;
@@ -528,6 +613,13 @@ void hmsv_db_destroy(hmsv_db *db) {
 int64_t hmsv_db_nseq(const hmsv_db *db) { return db ? db->nseq : -1; }
 int64_t hmsv_db_residues(const hmsv_db *db) { return db ? db->residues : -1; }
 int64_t hmsv_db_padded_rows(const hmsv_db *db) { return db ? db->rows : -1; }
+int32_t hmsv_db_table_rows(const hmsv_db *db) { return db ? db->table_rows : -1; }
+
+hmsv_status hmsv_db_default_plan(const hmsv_db *db, int32_t is_msv, int32_t M, hmsv_plan *plan) {
+    if (!db || !plan || M < 1) return HMSV_EINVAL;
+    if (M > HMSV_MAX_M) return HMSV_EUNSUPPORTED;
+    return resolve_plan(is_msv ? 1 : 0, M, db->table_rows, nullptr, plan);
+}
 
 hmsv_status hmsv_default_plan(int32_t is_msv, int32_t M, hmsv_plan *plan) {
     if (!plan) return HMSV_EINVAL;
@@ -632,10 +724,7 @@ hmsv_status hmsv_split_info(const hmsv_db *db, int64_t first, int64_t count, int
     if (M < 1) return HMSV_EINVAL;
     if (M > HMSV_MAX_M) return HMSV_EUNSUPPORTED;
     hmsv_plan plan;
-    hmsv_status st = plan_in ? HMSV_OK : hmsv_default_plan(is_msv ? 1 : 0, M, &plan);
-    if (st != HMSV_OK) return st;
-    if (plan_in) plan = *plan_in;
-    st = check_plan(&plan, M);
+    hmsv_status st = resolve_plan(is_msv ? 1 : 0, M, db->table_rows, plan_in, &plan);
     if (st != HMSV_OK) return st;
     const KernelEntry *e = registry().find(is_msv ? 1 : 0, plan.G, plan.Q);
     if (!e) return HMSV_ENOKERNEL;
@@ -643,7 +732,7 @@ hmsv_status hmsv_split_info(const hmsv_db *db, int64_t first, int64_t count, int
     if (first < 0 || count < 0 || first > db->nseq || count > db->nseq - first) return HMSV_EINVAL;
     *nsplit = *nsegs = *seg_rows = 0;
     if (count == 0) return HMSV_OK;
-    const int blocks = grid_blocks(e, plan, count);
+    const int blocks = grid_blocks(e, plan, count, db->table_rows);
     if (blocks <= 0) return HMSV_EDEVICE;
     KArgs a{};
     plan_split(db, first, count, (int64_t)blocks * plan.waves_per_block * (64 / plan.G), M, a);
@@ -669,6 +758,15 @@ hmsv_status hmsv_p7_quantize(const double *emis, const double *trans, const doub
         for (int k = 0; k < M; ++k)
             msc[(size_t)x * M + k] = (int16_t)(x < HMSV_K
                 ? p7_score(emis[(size_t)k * HMSV_K + x] / bg[x]) : -32768);
+    for (const Degenerate &d : kDegenerate) {
+        for (int k = 0; k < M; ++k) {
+            double mean = 0.0;
+            int32_t v = -32768;
+            if (degenerate_mean(emis + (size_t)k * HMSV_K, bg, d, &mean))
+                v = (int32_t)std::max(-32768.0, std::min(32767.0, rhaz((double)kP7Units * mean)));
+            msc[(size_t)d.code * M + k] = (int16_t)v;
+        }
+    }
     for (int t = 0; t < 7; ++t)
         for (int k = 0; k < M; ++k)
             trans_out[(size_t)t * M + k] = (int16_t)p7_score(trans[(size_t)k * 7 + t]);
@@ -723,14 +821,23 @@ hmsv_status hmsv_p7_score(const hmsv_p7_profile *prof, const hmsv_db *db, int16_
     } else {
         hmsv_status st = hmsv_p7_default_plan(prof->M, &plan);
         if (st != HMSV_OK) return st;
+        // with the degenerate rows the image may no longer fit: the
+        // narrowest group that still holds it
+        for (int G : {4, 8, 16, 32, 64}) {
+            if (p7_lds_bytes(plan.G, plan.Q, db->table_rows) <= (size_t)kLdsBytes) break;
+            const int Q = (prof->M + 1 + 2 * G - 1) / (2 * G);
+            if (Q > (G == 64 ? 22 : 16) || !registry().find_p7(G, Q)) continue;
+            plan.G = G;
+            plan.Q = Q;
+        }
     }
     if (plan.G < 1 || plan.G > 64 || (64 % plan.G) != 0 || plan.Q < 1 ||
         plan_nodes(plan.G, plan.Q) < prof->M || plan.blocks < 0 ||
         plan.waves_per_block < 1 || plan.waves_per_block > 8)
         return HMSV_EINVAL;
-    if (p7_lds_bytes(plan.G, plan.Q) > (size_t)kLdsBytes) return HMSV_EUNSUPPORTED;
     const P7KernelEntry *e = registry().find_p7(plan.G, plan.Q);
     if (!e) return HMSV_ENOKERNEL;
+    if (p7_lds_bytes(plan.G, plan.Q, db->table_rows) > (size_t)kLdsBytes) return HMSV_EUNSUPPORTED;
     if (db->nseq == 0) return HMSV_OK;
     int blocks = plan.blocks;
     if (blocks == 0) {
@@ -738,7 +845,7 @@ hmsv_status hmsv_p7_score(const hmsv_p7_profile *prof, const hmsv_db *db, int16_
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return HMSV_EDEVICE;
-        const int per_cu = e->occupancy(plan.waves_per_block);
+        const int per_cu = e->occupancy(plan.waves_per_block, db->table_rows);
         if (per_cu <= 0) return HMSV_EDEVICE;
         blocks = per_cu * cus;
         const int64_t groups_per_block = (int64_t)plan.waves_per_block * (64 / plan.G);
@@ -758,6 +865,7 @@ hmsv_status hmsv_p7_score(const hmsv_p7_profile *prof, const hmsv_db *db, int16_
     a.score = score;
     a.flag = flags;
     a.image = (uint32_t *)((char *)workspace + kWsCounterBytes);
+    a.rows = db->table_rows;
     if (e->launch(a, plan.waves_per_block, blocks, stream) != hipSuccess) return HMSV_EDEVICE;
     return HMSV_OK;
 }
@@ -782,13 +890,8 @@ hmsv_status hmsv_batch_create(const hmsv_query *queries, int32_t nq, const hmsv_
         if (((uintptr_t)q.workspace & 255u) != 0) return HMSV_EINVAL;
         for (int k = 0; k < i; ++k)
             if (queries[k].workspace == q.workspace) return HMSV_EINVAL;
-        if (q.plan.G == 0) {
-            st = hmsv_default_plan(q.is_msv ? 1 : 0, q.prof.M, &plans[i]);
-            if (st != HMSV_OK) return st;
-        } else {
-            plans[i] = q.plan;
-        }
-        st = check_plan(&plans[i], q.prof.M);
+        st = resolve_plan(q.is_msv ? 1 : 0, q.prof.M, db->table_rows,
+                          q.plan.G == 0 ? nullptr : &q.plan, &plans[i]);
         if (st != HMSV_OK) return st;
         if (!registry().find(q.is_msv ? 1 : 0, plans[i].G, plans[i].Q)) return HMSV_ENOKERNEL;
     }

@@ -10,6 +10,9 @@ namespace hmsv {
 // Table rows staged in LDS: the 20 amino acids plus one non-scoring row.
 // The database packer maps every code 20..31 to 20.
 constexpr int kRows = 21;
+// With the degenerate residue codes 21..26 (B, J, Z, U, O, X) the images
+// hold rows 0..26; a database without them needs only the first 21.
+constexpr int kDegenRows = 27;
 constexpr uint8_t kInvalidCode = 20;
 constexpr int kLdsBytes = 160 * 1024;
 
@@ -63,6 +66,7 @@ struct KArgs {
     uint32_t *counter;     // work-queue head, zeroed by the prep kernel
     uint32_t *image;       // LDS image of the profile (workspace), 16-byte aligned
     int32_t *best;         // MSV: per table row, max over nodes of dbias - cost (workspace)
+    int32_t rows;          // table rows of the LDS images: kRows or kDegenRows
     // split sequences: records [0, nsplit) of the range are replaced by
     // nsegs segment records (workspace), processed first
     SeqRec *segs;          // [kMaxSegs] segment records (workspace)
@@ -103,7 +107,7 @@ constexpr size_t ws_bytes(int64_t nseq) { return kWsWinOff + 16 * (size_t)(nseq 
 typedef hipError_t (*LaunchFn)(const KArgs &, int waves_per_block, int blocks,
                                hipStream_t);
 typedef hipError_t (*ExactLaunchFn)(const KArgs &, int cus, hipStream_t);
-typedef int (*OccupancyFn)(int waves_per_block);
+typedef int (*OccupancyFn)(int waves_per_block, int rows);
 
 struct KernelEntry {
     int is_msv;
@@ -113,8 +117,9 @@ struct KernelEntry {
     OccupancyFn occupancy;
 };
 
-// P7Viterbi's LDS image rows: 21 of match emissions (residue rows, row 20 =
-// -inf), then 7 of transitions (see P7Args).
+// P7Viterbi's LDS image rows: 21 (or 27, with the degenerate codes) of
+// match emissions (residue rows, row 20 = -inf), then 7 of transitions (see
+// P7Args).  The chunk layout is chosen for kP7Rows rows.
 constexpr int kP7EmisRows = kRows;
 constexpr int kP7Rows = kRows + 7;
 
@@ -154,9 +159,13 @@ constexpr LdsLayout lds_layout(int G, int Q, int rows = kRows) {
     return L;
 }
 
-inline size_t lds_bytes(int G, int Q) { return (size_t)kRows * lds_layout(G, Q).RS * 4; }
-inline size_t p7_lds_bytes(int G, int Q) {
-    return (size_t)kP7Rows * lds_layout(G, Q, kP7Rows).RS * 4;
+// LDS bytes of an image of `rows` table rows (the chunk layout is the one
+// chosen for kRows, or kP7Rows, rows).
+inline size_t lds_bytes(int G, int Q, int rows = kRows) {
+    return (size_t)rows * lds_layout(G, Q).RS * 4;
+}
+inline size_t p7_lds_bytes(int G, int Q, int rows = kRows) {
+    return (size_t)(rows + 7) * lds_layout(G, Q, kP7Rows).RS * 4;
 }
 
 // A group of G lanes with Q registers covers nodes 1..2GQ-1 (slot 0 is a
@@ -183,6 +192,8 @@ struct P7Args {
     int16_t *score;
     uint8_t *flag;
     uint32_t *image;       // the LDS image (workspace)
+    int32_t rows;          // emission rows (kRows or kDegenRows); the 7
+                           // transition rows follow them
 };
 
 constexpr int kMaxP7G = 64;

@@ -26,7 +26,8 @@
 // slots, max-ing it in, until no element's last D changes (max and a
 // saturating add of a fixed score commute, so the result is the sequential
 // chain's).  Scores come from LDS: 21 rows of match emissions by residue
-// and 7 rows of transitions, in the MSV image's conflict-free layout.
+// (27 with the degenerate codes) and 7 rows of transitions, in the MSV
+// image's conflict-free layout.
 // The special states are updated once per row from the group's maximum.
 //
 // Sequences are dealt out statically: lane group g of N takes records g,
@@ -53,17 +54,17 @@ constexpr int kP7Pos = 32767;
 constexpr int kP7Half = -32;          // E->J and E->C: 32 log2(1/2)
 __device__ __forceinline__ int sat16(int v) { return v < kP7Neg ? kP7Neg : (v > kP7Pos ? kP7Pos : v); }
 
-// Score of table row r (0..20 emissions by residue, 21.. transitions) at
-// slot s (node s; slot 0 is the dummy).
+// Score of table row r (emissions by residue below a.rows, transitions
+// from there) at slot s (node s; slot 0 is the dummy).
 __device__ __forceinline__ int p7_slot_score(const P7Args &a, int r, int s) {
     const int M = a.M;
-    if (r < kP7EmisRows) {
+    if (r < a.rows) {
         if (s < 1 || s > M || r == kInvalidCode) return kP7Neg;
         return a.msc[r * M + s - 1];
     }
     // transitions: MMp, IMp, DMp, MDp, DDp come from node s - 1; MI, II
     // from node s (their table rows: MM 0, MI 1, MD 2, IM 3, II 4, DM 5, DD 6)
-    const int t = r - kP7EmisRows;
+    const int t = r - a.rows;
     const int from = (t == kP7MI || t == kP7II) ? s : s - 1;
     if (from < 1 || from > M) return kP7Neg;
     const int row = t == kP7MMp ? 0 : t == kP7IMp ? 3 : t == kP7DMp ? 5 : t == kP7MI ? 1
@@ -71,13 +72,13 @@ __device__ __forceinline__ int p7_slot_score(const P7Args &a, int r, int s) {
     return a.trans[row * M + from - 1];
 }
 
-// The LDS image (kP7Rows rows of the lds_layout(G, Q) shape), one dword per
-// thread.
+// The LDS image (a.rows + 7 rows of the lds_layout(G, Q, kP7Rows) shape),
+// one dword per thread.
 template <int G, int Q>
 __global__ void __launch_bounds__(256) p7_prep_kernel(P7Args a) {
     constexpr LdsLayout D = lds_layout(G, Q, kP7Rows);
     const int idx = (int)(blockIdx.x * 256 + threadIdx.x);
-    if (idx >= kP7Rows * D.RS) return;
+    if (idx >= (a.rows + 7) * D.RS) return;
     const int x = idx / D.RS;
     int rem = idx - x * D.RS;
     int w, q0;
@@ -116,7 +117,7 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     {
         const uint4 *src = (const uint4 *)a.image;
         uint4 *dst = (uint4 *)lds;
-        constexpr int n16 = kP7Rows * RS / 4;
+        const int n16 = (a.rows + 7) * (RS / 4);
         for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
     }
     __syncthreads();
@@ -142,7 +143,7 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     auto comp = [](const uint4 &v, int u) -> uint32_t {
         return u == 0 ? v.x : u == 1 ? v.y : u == 2 ? v.z : v.w;
     };
-    constexpr uint32_t rT = kP7EmisRows;     // first transition row
+    const uint32_t rT = (uint32_t)a.rows;    // first transition row
 
     const int ngroups = (int)(gridDim.x * (blockDim.x / G));
     const int gid = (int)(blockIdx.x * (blockDim.x / G) + threadIdx.x / G);
@@ -345,12 +346,13 @@ constexpr int kP7MaxWaves = 8;
 // The LDS image, then the filter kernel.
 template <int G, int Q>
 hipError_t launch_p7(const P7Args &a, int wpb, int blocks, hipStream_t s) {
-    constexpr int n = kP7Rows * lds_layout(G, Q, kP7Rows).RS;
+    if (a.rows != kRows && a.rows != kDegenRows) return hipErrorInvalidValue;
+    const int n = (a.rows + 7) * lds_layout(G, Q, kP7Rows).RS;
     if (wpb < 1 || wpb > kP7MaxWaves) return hipErrorInvalidValue;
     hipLaunchKernelGGL((p7_prep_kernel<G, Q>), dim3((n + 255) / 256), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds = p7_lds_bytes(G, Q);
+    const size_t lds = p7_lds_bytes(G, Q, a.rows);
     if (lds > 64 * 1024) {
         e = hipFuncSetAttribute((const void *)p7_kernel<G, Q, 512>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -362,10 +364,10 @@ hipError_t launch_p7(const P7Args &a, int wpb, int blocks, hipStream_t s) {
 
 // Resident blocks of wpb wavefronts per CU (0 on error).
 template <int G, int Q>
-int occupancy_p7(int wpb) {
+int occupancy_p7(int wpb, int rows) {
     if (wpb < 1 || wpb > kP7MaxWaves) return 0;
     int nb = 0;
-    const size_t lds = p7_lds_bytes(G, Q);
+    const size_t lds = p7_lds_bytes(G, Q, rows);
     if (hipFuncSetAttribute((const void *)p7_kernel<G, Q, 512>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;

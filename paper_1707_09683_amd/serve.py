@@ -32,7 +32,7 @@ import time
 import numpy as np
 import torch
 
-from . import Profile, Database, plan_for, score_range, workspace_bytes, quantize
+from . import Profile, Database, db_default_plan, score_range, workspace_bytes, quantize
 from .autotune import lds_bytes
 
 
@@ -75,7 +75,7 @@ class Request:
                  "future", "chunks", "next_chunk", "remaining", "slot", "event", "lds",
                  "cells")
 
-    def __init__(self, rid, filt, profile, plan, t_arrival):
+    def __init__(self, rid, filt, profile, plan, t_arrival, table_rows=21):
         self.rid = rid
         self.filt = filt
         self.profile = profile
@@ -90,7 +90,9 @@ class Request:
         self.remaining = 0
         self.slot = None
         self.event = None
-        self.lds = lds_bytes(plan.G, plan.Q)
+        # the image has table_rows rows (27 with degenerate codes) of the
+        # 21-row figure's size each
+        self.lds = lds_bytes(plan.G, plan.Q) * table_rows // 21
         self.cells = 0
 
 
@@ -160,11 +162,12 @@ class Server:
         q = quantize(emissions, self.bg)
         prof = Profile(torch.from_numpy(q["cost"]).to(self.device, non_blocking=False),
                        torch.from_numpy(q["sc"]).to(self.device, non_blocking=False), q["dbias"])
-        plan = plan_for(filt, prof.M)
+        plan = db_default_plan(self.db, filt, prof.M)
         with self._cv:
             self._rid += 1
             r = Request(self._rid, filt, prof, plan,
-                        time.perf_counter() if t_arrival is None else t_arrival)
+                        time.perf_counter() if t_arrival is None else t_arrival,
+                        self.db.table_rows)
             self._queue.append(r)
             self._cv.notify()
         return r.future

@@ -102,7 +102,8 @@ def test_p7_largest_plans(hm, G, Q, M):
 
 def test_p7_edge_lengths_and_codes(hm):
     """Empty sequences, lengths around the 16-residue step, one long
-    sequence, and non-scoring codes 20..31 inside sequences."""
+    sequence, and codes 20..31 inside sequences (non-scoring 20, 27..31 and
+    the degenerate 21..26)."""
     M = 64
     e, t = _profile(21, M)
     lens = [0, 1, 2, 3, 4, 15, 16, 17, 31, 32, 33, 0, 5000, 63, 64, 65, 0, 1]

@@ -7,9 +7,12 @@ the library accepts up to 64.  Here the tables are drawn directly
 residues, a consensus residue per node, and runs of consensus residues
 implanted so that sequences land on both sides of the J-state level
 (base + tec) and of the overflow level (255 - dbias), including dbias 61..64
-where overflow comes before the J state can open.  The GPU copy of each
-table carries random bytes in rows 20..31, which the kernels must ignore
-(codes 20..31 score as -inf); the oracle gets rows of 255 there."""
+where overflow comes before the J state can open.  Rows 21..26 of each
+table score the degenerate codes (B, J, Z, U, O, X), which the databases
+of M < 2560 carry (their images hold 27 rows; M = 3839 only fits 21).  The
+GPU copy of each table carries random bytes in rows 20 and 27..31, which
+the kernels must ignore (those codes score as -inf); the oracle gets rows
+of 255 there."""
 import numpy as np
 import pytest
 
@@ -32,11 +35,11 @@ def hm():
     return m
 
 
-def _plans(hm, M):
+def _plans(hm, M, rows):
     out = []
     for G in (1, 2, 4, 8, 16, 32, 64):
         Q = -(-(M + 1) // (2 * G))
-        if Q <= 32 and 0 < hm.plan_lds_bytes(G, Q) <= 160 * 1024:
+        if Q <= 32 and 0 < hm.plan_lds_bytes(G, Q) * rows // 21 <= 160 * 1024:
             out.append((G, Q))
     return out
 
@@ -47,11 +50,20 @@ def _database(rng, cons, M):
     carrying 1..2 consensus runs each (their scores are exact sums of the
     runs' gains, so they land densely around the J-state and overflow
     levels); four long sequences with runs (cut into segments by the
-    library).  About 0.3% of the random residues are codes 20..31."""
+    library).  About 0.3% of the random residues are one code of 20..31
+    (above 2559 nodes a degenerate draw becomes 27), and for M < 2560 another
+    0.5% are degenerate codes 21..26."""
     n, hi = (700, 500) if M < 1000 else (150, 400)
     db = synth.random_db(rng, n, 0, hi)
     synth.implant_consensus(rng, db.res, db.offsets, cons, 0.6, 40)
-    db.res[rng.random(db.res.size) < 0.003] = rng.integers(20, 32)
+    code = int(rng.integers(20, 32))
+    if M >= 2560 and 21 <= code <= 26:
+        code = 27
+    db.res[rng.random(db.res.size) < 0.003] = code
+    if M < 2560:
+        r3 = np.random.default_rng(11000 + M)
+        d = r3.random(db.res.size) < 0.005
+        db.res[d] = r3.integers(21, 27, size=int(d.sum()))
     lad = synth.random_db(rng, n, 1, hi)
     lad.res[:] = 20
     synth.implant_consensus(rng, lad.res, lad.offsets, cons, 1.0, 24, (1, 2))
@@ -71,18 +83,23 @@ def test_table_profiles_every_sequence(hm, dbias, M):
     rng = np.random.default_rng(7000 + 17 * dbias + M)
     cost, cons = synth.random_cost_table(rng, M, dbias)
     db = _database(rng, cons, M)
+    # degenerate rows 21..26: costs of their own, read by both sides
+    r2 = np.random.default_rng(9000 + 17 * dbias + M)
+    cost[21:27] = np.clip(dbias + r2.integers(-3, 12, size=(6, M)), 0, 255)
     oprof = oq.from_costs(cost, dbias)
-    # the library's copy: rows 20..31 hold random bytes it must not read
+    # the library's copy: rows 20 and 27..31 hold random bytes it must not read
     g_cost = cost.copy()
-    g_cost[20:] = rng.integers(0, 256, size=g_cost[20:].shape)
     g_sc = np.maximum(-128, dbias - cost.astype(np.int64)).astype(np.int8)
-    g_sc[20:] = rng.integers(-128, 128, size=g_sc[20:].shape)
+    for rows in (slice(20, 21), slice(27, 32)):
+        g_cost[rows] = rng.integers(0, 256, size=g_cost[rows].shape)
+        g_sc[rows] = rng.integers(-128, 128, size=g_sc[rows].shape)
     prof = hm.Profile(torch.from_numpy(g_cost).cuda(), torch.from_numpy(g_sc).cuda(), dbias)
     gdb = hm.Database(db.res, db.offsets)
+    assert gdb.table_rows == (27 if M < 2560 else 21)
     for filt in ("msv", "ssv"):
         es, ef = oracle.score_db(filt, oprof, db.res, db.offsets)
         fn = hm.msv_score if filt == "msv" else hm.ssv_score
-        for G, Q in _plans(hm, M):
+        for G, Q in _plans(hm, M, gdb.table_rows):
             print(f"case tables {filt} dbias={dbias} M={M} G={G} Q={Q}", flush=True)
             s, f = fn(prof, gdb, plan=hm.make_plan(G, Q, 4, 0))
             torch.cuda.synchronize()
