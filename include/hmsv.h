@@ -141,6 +141,23 @@ typedef struct {
  * Synchronous.  Fails with HMSV_EINVAL on null pointers, decreasing offsets
  * or codes >= 32; HMSV_EUNSUPPORTED if the packed size reaches 2^32 bytes,
  * a sequence is longer than 2^24 - 4 residues, or nseq >= 2^31. */
+/* Protein FASTA text (host memory, n bytes) -> residue codes and offsets
+ * for hmsv_db_create.  A record starts at a '>' and its header is the rest
+ * of that line; the lines up to the next '>' are its sequence.  Sequence
+ * letters map case-insensitively to ACDEFGHIKLMNPQRSTVWY = 0..19 and the
+ * degenerate B J Z U O X = 21..26; whitespace, digits, '*' (stop) and the
+ * gap symbols '-' '.' are skipped.  Any other byte, or a residue before the
+ * first header, is HMSV_EINVAL with its byte offset in *err_at (if
+ * err_at is not NULL; -1 otherwise).
+ * Two calls: first with res, offsets and names NULL, which sets *nres and
+ * *nseq; then with caller buffers res [*nres] uint8, offsets [*nseq + 1]
+ * int64 and names [*nseq][2] int64 (each header's byte offset in text and
+ * its length, without the '>' and a trailing '\r'), *nres and *nseq
+ * holding those counts (HMSV_EINVAL if the text does not match them).
+ * res may stay NULL in the second call to get offsets and names only. */
+hmsv_status hmsv_fasta_parse(const char *text, int64_t n, uint8_t *res, int64_t *offsets,
+                             int64_t *names, int64_t *nres, int64_t *nseq, int64_t *err_at);
+
 typedef struct hmsv_db hmsv_db;
 hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t nseq,
                            hmsv_db **out);

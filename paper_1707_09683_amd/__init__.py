@@ -77,6 +77,9 @@ _lib.hmsv_db_destroy.argtypes = [_P]
 for _f in ("hmsv_db_nseq", "hmsv_db_residues", "hmsv_db_padded_rows"):
     getattr(_lib, _f).restype = _i64
     getattr(_lib, _f).argtypes = [_P]
+_lib.hmsv_fasta_parse.restype = ctypes.c_int
+_lib.hmsv_fasta_parse.argtypes = [ctypes.c_char_p, _i64, _P, _P, _P, ctypes.POINTER(_i64),
+                                  ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
 _lib.hmsv_db_table_rows.restype = _i32
 _lib.hmsv_db_table_rows.argtypes = [_P]
 _lib.hmsv_db_default_plan.restype = ctypes.c_int
@@ -132,6 +135,7 @@ EXPORTED = ("hmsv_strerror", "hmsv_tbm", "hmsv_tjb", "hmsv_quantize", "hmsv_db_c
             "hmsv_msv_score_range", "hmsv_ssv_score_range", "hmsv_db_order",
             "hmsv_split_info", "hmsv_score_nats", "hmsv_gumbel_pvalue",
             "hmsv_msv_score_noalloc", "hmsv_db_table_rows", "hmsv_db_default_plan",
+            "hmsv_fasta_parse",
             "hmsv_p7_quantize", "hmsv_p7_length_model",
             "hmsv_p7_lds_bytes", "hmsv_p7_default_plan", "hmsv_p7_score")
 
@@ -235,6 +239,32 @@ def default_plan(filt: str, M: int) -> Plan:
     _check(_lib.hmsv_default_plan(1 if filt == "msv" else 0, int(M), ctypes.byref(p)),
            "hmsv_default_plan")
     return p
+
+
+def parse_fasta(text: bytes):
+    """Protein FASTA bytes -> (headers list[str], residues uint8 [n],
+    offsets int64 [nseq + 1]), parsed by the library (hmsv_fasta_parse)."""
+    if isinstance(text, str):
+        text = text.encode()
+    nres, nseq, err = _i64(0), _i64(0), _i64(-1)
+    rc = _lib.hmsv_fasta_parse(text, len(text), None, None, None, ctypes.byref(nres),
+                               ctypes.byref(nseq), ctypes.byref(err))
+    if rc != OK:
+        raise HmsvError(rc, f"hmsv_fasta_parse (byte {err.value})")
+    res = np.empty(max(1, nres.value), np.uint8)
+    off = np.empty(nseq.value + 1, np.int64)
+    names = np.empty((max(1, nseq.value), 2), np.int64)
+    _check(_lib.hmsv_fasta_parse(text, len(text), _np_ptr(res), _np_ptr(off), _np_ptr(names),
+                                 ctypes.byref(nres), ctypes.byref(nseq), ctypes.byref(err)),
+           "hmsv_fasta_parse")
+    heads = [text[a:a + n].decode(errors="replace") for a, n in names[:nseq.value]]
+    return heads, res[:nres.value], off
+
+
+def read_fasta(path):
+    """A protein FASTA file -> (headers, residues, offsets); see parse_fasta."""
+    with open(path, "rb") as f:
+        return parse_fasta(f.read())
 
 
 def db_default_plan(db, filt: str, M: int) -> Plan:

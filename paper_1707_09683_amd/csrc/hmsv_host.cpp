@@ -508,6 +508,82 @@ hmsv_status hmsv_quantize(const double *emis, const double *bg, int32_t M, uint8
     return HMSV_OK;
 }
 
+// ---- FASTA ------------------------------------------------------------------
+
+namespace {
+// Residue code of a sequence byte: 0..31, -1 to skip (whitespace, digits,
+// stop and gap symbols), -2 if invalid.
+int fasta_code(unsigned char c) {
+    static const char kAlpha[] = "ACDEFGHIKLMNPQRSTVWY";
+    if (c >= 'a' && c <= 'z') c = (unsigned char)(c - 'a' + 'A');
+    for (int i = 0; i < HMSV_K; ++i)
+        if (kAlpha[i] == (char)c) return i;
+    switch (c) {
+    case 'B': return 21;
+    case 'J': return 22;
+    case 'Z': return 23;
+    case 'U': return 24;
+    case 'O': return 25;
+    case 'X': return 26;
+    case ' ': case '\t': case '\r': case '\n': case '\v': case '\f':
+    case '*': case '-': case '.':
+        return -1;
+    default:
+        return (c >= '0' && c <= '9') ? -1 : -2;
+    }
+}
+}  // namespace
+
+hmsv_status hmsv_fasta_parse(const char *text, int64_t n, uint8_t *res, int64_t *offsets,
+                             int64_t *names, int64_t *nres, int64_t *nseq, int64_t *err_at) {
+    if ((!text && n > 0) || n < 0 || !nres || !nseq) return HMSV_EINVAL;
+    const bool fill = res || offsets || names;
+    if (fill && (!offsets || !names)) return HMSV_EINVAL;
+    const int64_t cap_res = fill ? *nres : 0, cap_seq = fill ? *nseq : 0;
+    int64_t r = 0, s = 0;
+    if (err_at) *err_at = -1;
+    int64_t i = 0;
+    while (i < n) {
+        const unsigned char c = (unsigned char)text[i];
+        if (c == '>') {
+            // header: the rest of the line
+            int64_t e = i + 1;
+            while (e < n && text[e] != '\n') ++e;
+            int64_t hl = e - (i + 1);
+            if (hl > 0 && text[i + hl] == '\r') --hl;
+            if (fill) {
+                if (s >= cap_seq) return HMSV_EINVAL;
+                offsets[s] = r;
+                names[2 * s] = i + 1;
+                names[2 * s + 1] = hl;
+            }
+            ++s;
+            i = e < n ? e + 1 : e;
+            continue;
+        }
+        const int code = fasta_code(c);
+        if (code == -2 || (code >= 0 && s == 0)) {
+            if (err_at) *err_at = i;
+            return HMSV_EINVAL;
+        }
+        if (code >= 0) {
+            if (fill) {
+                if (r >= cap_res) return HMSV_EINVAL;
+                if (res) res[r] = (uint8_t)code;
+            }
+            ++r;
+        }
+        ++i;
+    }
+    if (fill) {
+        if (s != cap_seq || r != cap_res) return HMSV_EINVAL;
+        offsets[s] = r;
+    }
+    *nres = r;
+    *nseq = s;
+    return HMSV_OK;
+}
+
 hmsv_status hmsv_db_create(const uint8_t *res, const int64_t *offsets, int64_t nseq,
                            hmsv_db **out) {
     if (!out || !offsets || nseq < 0) return HMSV_EINVAL;

@@ -193,3 +193,36 @@ def test_degenerate_batch_equals_plain(hm):
         assert np.array_equal(b.flags[i].cpu().numpy(), ef), (i, Ms[i], f)
     b.close()
     gdb.close()
+
+
+def test_fasta_to_scores(hm):
+    """FASTA text (made-up sequences with degenerate letters) through the
+    library's parser into a database, scored by all three filters."""
+    rng = np.random.default_rng(12)
+    M = 60
+    e = synth.sample_emissions(rng, M)
+    t = synth.sample_transitions(rng, M)
+    letters = np.array(list(synth.ALPHABET) + ["?"] + list("BJZUOX"))
+    L = rng.integers(0, 400, size=300).astype(np.int64)
+    res, off = synth.sample_residues(rng, L)
+    synth.implant(rng, res, off, [e], 0.2)
+    _sprinkle(rng, res, 0.03)
+    res[res == 20] = 26           # '?' has no letter: write X
+    res[res >= 27] = 26
+    text = "".join(f">r{i}\n" + "".join(letters[res[off[i]:off[i + 1]]]) + "\n"
+                   for i in range(len(L)))
+    heads, r2, o2 = hm.parse_fasta(text)
+    assert np.array_equal(r2, res) and np.array_equal(o2, off)
+    gdb = hm.Database(r2, o2)
+    print("case fasta end to end", flush=True)
+    for filt in ("msv", "ssv"):
+        fn = hm.msv_score if filt == "msv" else hm.ssv_score
+        s, f = fn(hm.Profile.from_emissions(e, synth.BG), gdb)
+        torch.cuda.synchronize()
+        _check((s.cpu().numpy(), f.cpu().numpy()),
+               oracle.score_db(filt, oq.quantize(e, synth.BG), res, off), f"fasta {filt}")
+    s, f = hm.p7_score(hm.P7Profile.from_probabilities(e, t, synth.BG), gdb)
+    torch.cuda.synchronize()
+    _check((s.cpu().numpy(), f.cpu().numpy()),
+           oracle.p7_score_db(op7.quantize(e, t, synth.BG), res, off), "fasta p7")
+    gdb.close()
