@@ -201,6 +201,37 @@ def time_plain(hm, torch, filt, prof, gdb, plan, steps, warmup):
     return wall, kern, kern_median, score, flags
 
 
+def layout_leg(hm, h):
+    """Padding of the database layouts on the headline database: this
+    library's records (each sequence's rows rounded up to the kernel's
+    16-row step, or 8 for groups of 16+ lanes) against the paper's
+    warp-based blocks (Alg. 1) at the paper's K40 shape (15 SMX x 32 warps,
+    128 columns) and at this GPU's (the headline plan's resident wavefronts,
+    64/G sequences each).  Host arithmetic only."""
+    L = np.asarray(h["db"].lengths, dtype=np.int64)
+    G, Q, wpb = h["plan"].G, h["plan"].Q, h["plan"].waves_per_block
+    step = 16 if G < 16 else 8
+    rows = np.maximum(4, (L + 3) // 4 * 4)
+    run = int(((rows + step - 1) // step * step).sum())
+    real = int(L.sum())
+    out = {"this_layout": {"rows_run": run, "real": real,
+                           "padding_to_real": round((run - real) / real, 6),
+                           "balance": "dynamic queue; sequences above 1.5x the mean work "
+                                      "per lane group are split into segments"}}
+    nwaves = 256 * 4 * (4 if G < 64 else 2)
+    for name, nb, width in (("alg1_k40_shape", 15 * 32, 128),
+                            ("alg1_mi355x_shape", nwaves, 64 // G)):
+        _, _, st = hm.alg1_pack(L, nb, width)
+        out[name] = {"blocks": nb, "width": width, "prr": round(st["prr"], 7),
+                     "mean_height": round(st["mean_height"], 1),
+                     "sd_height": round(st["sd_height"], 1),
+                     "max_height": st["max_height"],
+                     "efficiency": round(st["efficiency"], 4),
+                     "mean_ending": round(st["mean_ending"], 1),
+                     "sd_ending": round(st["sd_ending"], 2)}
+    return out
+
+
 def headline(a, hm, torch, synth):
     t0 = time.time()
     w = synth.plain_msv_m400(nseq=a.nseq)
@@ -514,6 +545,7 @@ def main():
         extra["ssv"] = ssv_leg(a, hm, torch, synth, h)
         progress("p7 leg")
         extra["p7"] = p7_leg(a, hm, torch, synth, h)
+        extra["layout"] = layout_leg(hm, h)
     h["gdb"].close()
     if not a.no_extra:
         progress("batched leg")

@@ -141,6 +141,37 @@ typedef struct {
  * Synchronous.  Fails with HMSV_EINVAL on null pointers, decreasing offsets
  * or codes >= 32; HMSV_EUNSUPPORTED if the packed size reaches 2^32 bytes,
  * a sequence is longer than 2^24 - 4 residues, or nseq >= 2^31. */
+/* The paper's warp-based sequence blocks (Sec. 3.2, Alg. 1), as an
+ * alternative layout to compare against hmsv_db_create's (which hands
+ * sequences to lane groups dynamically): nblocks blocks (the paper: one per
+ * resident warp) of width columns (the paper: 128 sequences side by side).
+ * Sequences are placed longest first (ties in input order), each taking
+ * its residues plus one ending residue; the first nblocks x width seed the
+ * columns in order; every later one goes to the first column, sweeping
+ * down from where the previous one went, whose fill plus its own stays
+ * within the tallest column so far, or, when the sweep passes column 0,
+ * onto the last column (the sweep then restarts at the top).  A block's
+ * height is its tallest column; padding fills the other columns to it.
+ * lengths: host [nseq].  container: host [nseq] out, the column of each
+ * sequence in input order (may be NULL: then the ending statistics are
+ * -1).  heights: host [nblocks] out (may be NULL).  Host only, allocates
+ * host memory. */
+typedef struct {
+    int64_t real;          /* residues */
+    int64_t ending;        /* ending residues (one per sequence) */
+    int64_t padding;       /* padding residues */
+    int64_t max_height;    /* tallest block */
+    double mean_height;    /* block heights: mean and standard deviation */
+    double sd_height;
+    double mean_ending;    /* ending residues per block: mean and sd */
+    double sd_ending;
+    double prr;            /* padding / real (Table 2's PRR) */
+    double efficiency;     /* mean height / max height: busy share of a grid
+                              whose blocks all start together */
+} hmsv_alg1_stats;
+hmsv_status hmsv_alg1_pack(const int64_t *lengths, int64_t nseq, int32_t nblocks, int32_t width,
+                           int32_t *container, int64_t *heights, hmsv_alg1_stats *stats);
+
 /* Protein FASTA text (host memory, n bytes) -> residue codes and offsets
  * for hmsv_db_create.  A record starts at a '>' and its header is the rest
  * of that line; the lines up to the next '>' are its sequence.  Sequence

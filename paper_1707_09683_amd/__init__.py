@@ -77,6 +77,19 @@ _lib.hmsv_db_destroy.argtypes = [_P]
 for _f in ("hmsv_db_nseq", "hmsv_db_residues", "hmsv_db_padded_rows"):
     getattr(_lib, _f).restype = _i64
     getattr(_lib, _f).argtypes = [_P]
+class Alg1Stats(ctypes.Structure):
+    """hmsv_alg1_stats: the padding and balance of Alg. 1's blocks."""
+    _fields_ = [("real", _i64), ("ending", _i64), ("padding", _i64), ("max_height", _i64),
+                ("mean_height", ctypes.c_double), ("sd_height", ctypes.c_double),
+                ("mean_ending", ctypes.c_double), ("sd_ending", ctypes.c_double),
+                ("prr", ctypes.c_double), ("efficiency", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib.hmsv_alg1_pack.restype = ctypes.c_int
+_lib.hmsv_alg1_pack.argtypes = [_P, _i64, _i32, _i32, _P, _P, ctypes.POINTER(Alg1Stats)]
 _lib.hmsv_fasta_parse.restype = ctypes.c_int
 _lib.hmsv_fasta_parse.argtypes = [ctypes.c_char_p, _i64, _P, _P, _P, ctypes.POINTER(_i64),
                                   ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
@@ -135,7 +148,7 @@ EXPORTED = ("hmsv_strerror", "hmsv_tbm", "hmsv_tjb", "hmsv_quantize", "hmsv_db_c
             "hmsv_msv_score_range", "hmsv_ssv_score_range", "hmsv_db_order",
             "hmsv_split_info", "hmsv_score_nats", "hmsv_gumbel_pvalue",
             "hmsv_msv_score_noalloc", "hmsv_db_table_rows", "hmsv_db_default_plan",
-            "hmsv_fasta_parse",
+            "hmsv_fasta_parse", "hmsv_alg1_pack",
             "hmsv_p7_quantize", "hmsv_p7_length_model",
             "hmsv_p7_lds_bytes", "hmsv_p7_default_plan", "hmsv_p7_score")
 
@@ -239,6 +252,18 @@ def default_plan(filt: str, M: int) -> Plan:
     _check(_lib.hmsv_default_plan(1 if filt == "msv" else 0, int(M), ctypes.byref(p)),
            "hmsv_default_plan")
     return p
+
+
+def alg1_pack(lengths, nblocks: int, width: int):
+    """The paper's warp-based blocks (Alg. 1) for these sequence lengths:
+    (container per sequence, block heights, stats dict)."""
+    L = np.ascontiguousarray(lengths, dtype=np.int64)
+    cont = np.empty(max(1, L.size), np.int32)
+    heights = np.empty(int(nblocks), np.int64)
+    st = Alg1Stats()
+    _check(_lib.hmsv_alg1_pack(_np_ptr(L), L.size, int(nblocks), int(width), _np_ptr(cont),
+                               _np_ptr(heights), ctypes.byref(st)), "hmsv_alg1_pack")
+    return cont[:L.size], heights, st.as_dict()
 
 
 def parse_fasta(text: bytes):

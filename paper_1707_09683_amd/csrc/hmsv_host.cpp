@@ -508,6 +508,93 @@ hmsv_status hmsv_quantize(const double *emis, const double *bg, int32_t M, uint8
     return HMSV_OK;
 }
 
+// ---- the paper's warp-based sequence blocks (Sec. 3.2, Alg. 1) ---------------
+
+hmsv_status hmsv_alg1_pack(const int64_t *lengths, int64_t nseq, int32_t nblocks, int32_t width,
+                           int32_t *container, int64_t *heights, hmsv_alg1_stats *stats) {
+    if (nseq < 0 || (nseq > 0 && !lengths) || nblocks < 1 || width < 1 || !stats)
+        return HMSV_EINVAL;
+    const int64_t lines = (int64_t)nblocks * width;
+    if (lines > ((int64_t)1 << 31)) return HMSV_EUNSUPPORTED;
+    for (int64_t i = 0; i < nseq; ++i)
+        if (lengths[i] < 0) return HMSV_EINVAL;
+    // longest first, ties in input order
+    std::vector<int64_t> order((size_t)nseq);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return lengths[a] > lengths[b]; });
+    // each sequence fills its residues plus one ending residue
+    std::vector<int64_t> fill((size_t)lines, 0);
+    const int64_t seeds = std::min(lines, nseq);
+    int64_t max_len = 0;
+    for (int64_t x = 0; x < seeds; ++x) {
+        const int64_t sq = order[(size_t)x];
+        if (container) container[sq] = (int32_t)x;
+        fill[(size_t)x] = lengths[sq] + 1;
+        max_len = std::max(max_len, fill[(size_t)x]);
+    }
+    // the rest: a pointer sweeps the containers downward (continuing from
+    // the last placement) to the first whose fill stays within the longest
+    // container; below container 0 the sequence goes onto the last one and
+    // the sweep starts over
+    int64_t ptr = lines;
+    for (int64_t y = seeds; y < nseq; ++y) {
+        const int64_t sq = order[(size_t)y];
+        const int64_t need = lengths[sq] + 1;
+        int64_t target;
+        for (;;) {
+            --ptr;
+            if (ptr < 0) {
+                ptr = lines;
+                target = lines - 1;
+                break;
+            }
+            if (need + fill[(size_t)ptr] <= max_len) {
+                target = ptr;
+                break;
+            }
+        }
+        if (container) container[sq] = (int32_t)target;
+        fill[(size_t)target] += need;
+        max_len = std::max(max_len, fill[(size_t)target]);
+    }
+    int64_t padding = 0, real = 0, max_h = 0;
+    double sum_h = 0.0, sum_h2 = 0.0, sum_e = 0.0, sum_e2 = 0.0;
+    std::vector<int64_t> per_block_end((size_t)nblocks, 0);
+    for (int64_t i = 0; i < nseq; ++i) real += lengths[i];
+    if (container)
+        for (int64_t i = 0; i < nseq; ++i) per_block_end[(size_t)(container[i] / width)] += 1;
+    for (int32_t b = 0; b < nblocks; ++b) {
+        int64_t h = 0, tot = 0;
+        for (int32_t c = 0; c < width; ++c) {
+            const int64_t f = fill[(size_t)b * width + c];
+            h = std::max(h, f);
+            tot += f;
+        }
+        if (heights) heights[b] = h;
+        padding += (int64_t)width * h - tot;
+        max_h = std::max(max_h, h);
+        sum_h += (double)h;
+        sum_h2 += (double)h * (double)h;
+        const double e = (double)per_block_end[(size_t)b];
+        sum_e += e;
+        sum_e2 += e * e;
+    }
+    const double nb = (double)nblocks;
+    stats->real = real;
+    stats->ending = nseq;
+    stats->padding = padding;
+    stats->max_height = max_h;
+    stats->mean_height = sum_h / nb;
+    stats->sd_height = std::sqrt(std::max(0.0, sum_h2 / nb - (sum_h / nb) * (sum_h / nb)));
+    stats->mean_ending = container ? sum_e / nb : -1.0;
+    stats->sd_ending = container
+        ? std::sqrt(std::max(0.0, sum_e2 / nb - (sum_e / nb) * (sum_e / nb))) : -1.0;
+    stats->prr = real > 0 ? (double)padding / (double)real : 0.0;
+    stats->efficiency = max_h > 0 ? stats->mean_height / (double)max_h : 1.0;
+    return HMSV_OK;
+}
+
 // ---- FASTA ------------------------------------------------------------------
 
 namespace {
