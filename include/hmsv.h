@@ -414,17 +414,19 @@ typedef struct {
 /* LDS bytes per workgroup of a P7 plan's kernel (0 for an invalid shape). */
 size_t hmsv_p7_lds_bytes(int32_t G, int32_t Q);
 
-/* Default P7 plan for M: the narrowest lane group (4..64 lanes) whose lanes
- * hold the profile in at most 16 registers (22 for 64-lane groups), four
- * wavefronts per block, persistent grid. */
+/* Default P7 plan for M: the measured plan of the nearest profile-length
+ * bin (group width and waves per block, with the fewest registers per lane
+ * that hold the profile: at most 16, 22 for 64-lane groups), or the
+ * narrowest group that holds it; persistent grid. */
 hmsv_status hmsv_p7_default_plan(int32_t M, hmsv_plan *plan);
 
 /* Scores every sequence of the database: score[i] int16, flags[i] = 1 on
  * saturation (score 32767), both device arrays of nseq entries in the
  * caller's original order.  workspace: hmsv_workspace_bytes(nseq) bytes,
  * 256-byte aligned (calls sharing it must be ordered on one stream).  plan:
- * NULL for the default (plans take 1..8 waves per block).  Lane groups take the records (longest first) in
- * rounds, alternating direction; each sequence runs exactly its L rows.
+ * NULL for the default (plans take 1..8 waves per block).  Lane groups take
+ * the records (longest first) from a queue in the workspace as they finish
+ * one; each sequence runs exactly its L rows.
  * Asynchronous on the stream; allocates nothing.  Fails with HMSV_EINVAL on
  * null pointers or a bad plan, HMSV_EUNSUPPORTED for M > HMSV_P7_MAX_M,
  * HMSV_ENOKERNEL if the plan was not instantiated, HMSV_EDEVICE if the

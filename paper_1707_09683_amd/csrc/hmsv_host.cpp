@@ -952,18 +952,51 @@ size_t hmsv_p7_lds_bytes(int32_t G, int32_t Q) {
     return p7_lds_bytes(G, Q);
 }
 
+// P7Viterbi plans measured on MI355X (the 500,000-sequence lognormal
+// database, every (G, waves per block) with the fewest registers per lane):
+// profile length bin, group width, waves per block.
+struct P7Tuned {
+    int bin, G, wpb;
+};
+constexpr P7Tuned kP7Tuned[] = {
+    {30, 16, 8},  {64, 8, 8},   {100, 8, 8},  {200, 8, 4},   {400, 16, 4},  {700, 32, 8},
+    {1000, 32, 8}, {1500, 64, 8}, {2047, 64, 8}, {2400, 64, 8}, {2815, 64, 8},
+};
+
 hmsv_status hmsv_p7_default_plan(int32_t M, hmsv_plan *plan) {
     if (!plan || M < 1) return HMSV_EINVAL;
     if (M > HMSV_P7_MAX_M) return HMSV_EUNSUPPORTED;
-    // the narrowest group whose lanes hold the profile in at most 16
-    // registers (22 for 64-lane groups: profiles beyond 2047 nodes)
+    auto fits = [&](int G, int Q) {
+        return Q <= (G == 64 ? 22 : 16) && p7_lds_bytes(G, Q) <= (size_t)kLdsBytes &&
+               registry().find_p7(G, Q) != nullptr;
+    };
+    // the tuned bin nearest to M in log distance (ties to the smaller bin)
+    constexpr int nt = (int)(sizeof(kP7Tuned) / sizeof(kP7Tuned[0]));
+    int best = -1;
+    double bd = 0.0;
+    for (int i = 0; i < nt; ++i) {
+        const double d = std::fabs(std::log((double)kP7Tuned[i].bin) - std::log((double)M));
+        if (best < 0 || d < bd) {
+            best = i;
+            bd = d;
+        }
+    }
+    // its group width if that holds the profile, else the narrowest that does
+    const int G0 = kP7Tuned[best].G;
+    const int Q0 = (M + 1 + 2 * G0 - 1) / (2 * G0);
+    if (fits(G0, Q0)) {
+        plan->G = G0;
+        plan->Q = Q0;
+        plan->waves_per_block = kP7Tuned[best].wpb;
+        plan->blocks = 0;
+        return HMSV_OK;
+    }
     for (int G : {4, 8, 16, 32, 64}) {
         const int Q = (M + 1 + 2 * G - 1) / (2 * G);
-        if (Q > (G == 64 ? 22 : 16) || p7_lds_bytes(G, Q) > (size_t)kLdsBytes) continue;
-        if (!registry().find_p7(G, Q)) continue;
+        if (!fits(G, Q)) continue;
         plan->G = G;
         plan->Q = Q;
-        plan->waves_per_block = 4;
+        plan->waves_per_block = 8;
         plan->blocks = 0;
         return HMSV_OK;
     }
@@ -1028,6 +1061,7 @@ hmsv_status hmsv_p7_score(const hmsv_p7_profile *prof, const hmsv_db *db, int16_
     a.score = score;
     a.flag = flags;
     a.image = (uint32_t *)((char *)workspace + kWsCounterBytes);
+    a.aux = (int32_t *)workspace;
     a.rows = db->table_rows;
     if (e->launch(a, plan.waves_per_block, blocks, stream) != hipSuccess) return HMSV_EDEVICE;
     return HMSV_OK;

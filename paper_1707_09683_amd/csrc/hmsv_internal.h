@@ -192,6 +192,8 @@ struct P7Args {
     int16_t *score;
     uint8_t *flag;
     uint32_t *image;       // the LDS image (workspace)
+    int32_t *aux;          // workspace words: [0] max over nodes of D->M, [1] the
+                           // record queue (both set by the prep kernel)
     int32_t rows;          // emission rows (kRows or kDegenRows); the 7
                            // transition rows follow them
 };

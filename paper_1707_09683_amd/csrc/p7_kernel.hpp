@@ -30,10 +30,8 @@
 // image's conflict-free layout.
 // The special states are updated once per row from the group's maximum.
 //
-// Sequences are dealt out statically: lane group g of N takes records g,
-// 2N - 1 - g, 2N + g, ... (records run longest first, so alternating the
-// direction evens the groups' totals); the next record is loaded while the
-// current one runs.  A sequence runs exactly L rows: the rows of the last
+// Lane groups take records (longest first) from a queue as they finish
+// one; the next record is claimed and loaded while the current one runs.  A sequence runs exactly L rows: the rows of the last
 // 16-residue step past L leave the special states untouched.
 #pragma once
 #include <utility>
@@ -75,8 +73,29 @@ __device__ __forceinline__ int p7_slot_score(const P7Args &a, int r, int s) {
 // The LDS image (a.rows + 7 rows of the lds_layout(G, Q, kP7Rows) shape),
 // one dword per thread.
 template <int G, int Q>
-__global__ void __launch_bounds__(256) p7_prep_kernel(P7Args a) {
+__global__ void __launch_bounds__(256) p7_prep_kernel(P7Args a, int image_blocks) {
     constexpr LdsLayout D = lds_layout(G, Q, kP7Rows);
+    if ((int)blockIdx.x == image_blocks) {
+        // the last block: max over nodes of D->M into aux[0]
+        __shared__ int red[256];
+        int m = kP7Neg;
+        for (int k = threadIdx.x; k < a.M; k += 256) {
+            const int v = a.trans[5 * a.M + k];
+            m = v > m ? v : m;
+        }
+        red[threadIdx.x] = m;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h && red[threadIdx.x + h] > red[threadIdx.x])
+                red[threadIdx.x] = red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            a.aux[0] = red[0];
+            a.aux[1] = 0;               // the record queue
+        }
+        return;
+    }
     const int idx = (int)(blockIdx.x * 256 + threadIdx.x);
     if (idx >= (a.rows + 7) * D.RS) return;
     const int x = idx / D.RS;
@@ -121,6 +140,7 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
         for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
     }
     __syncthreads();
+    const int maxdm = a.aux[0];       // max over nodes of D->M (prep kernel)
 
     const int lane = threadIdx.x & 63;
     const int j = lane % G;
@@ -145,18 +165,21 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     };
     const uint32_t rT = (uint32_t)a.rows;    // first transition row
 
-    const int ngroups = (int)(gridDim.x * (blockDim.x / G));
-    const int gid = (int)(blockIdx.x * (blockDim.x / G) + threadIdx.x / G);
     const int nseq = a.nseq;
-    // the k-th record of this group: rounds of ngroups, direction alternating
-    auto record_of = [&](int k) -> int {
-        const int base = k * ngroups;
-        return base + ((k & 1) ? ngroups - 1 - gid : gid);
+    // Records come from a queue (a counter the prep kernel zeroed), longest
+    // first: a lane group claims its next record when it starts one, so a
+    // group that drew a long sequence draws fewer others.  `want`: the
+    // groups that claim (the whole wavefront takes part in the broadcast).
+    uint32_t *queue = (uint32_t *)(a.aux + 1);
+    auto claim = [&](bool want) -> int {
+        int v = 0;
+        if (want && gstart) v = (int)atomicAdd(queue, 1u);
+        if constexpr (G > 1) v = __shfl(v, lane - j);
+        return v;
     };
 
     s16x2 Mr[Q], Ir[Q], Dr[Q];
-    int k = 0;                   // this group's k-th record
-    int t = record_of(0);
+    int t = claim(true);
     uint4 rec = make_uint4(0u, 0u, 0u, 0u), rec16 = rec;
     uint32_t lm = 0u;
     if (t < nseq) {
@@ -164,11 +187,11 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
         rec16 = *((const uint4 *)(a.seqs + t) + 1);
         lm = a.lenmodel[t];
     }
-    // the next record, loaded while the current one runs
+    // the next record, claimed and loaded while the current one runs
+    int tn = claim(true);
     uint4 nrec = rec, nrec16 = rec16;
     uint32_t nlm = lm;
     auto prefetch = [&]() {
-        const int tn = record_of(k + 1);
         if (tn < nseq) {
             nrec = *(const uint4 *)(a.seqs + tn);
             nrec16 = *((const uint4 *)(a.seqs + tn) + 1);
@@ -218,72 +241,109 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
                 const uint32_t x = (word >> (8 * (r & 3))) & 0xffu;
                 const bool live = active && done + r < len;
                 const s16x2 bc = splat16(sat16(xB + a.tbm));
-                // ---- M, I, and D within each element ----------------------
-                s16x2 gM = as_s16x2(shift_in(s16_bits(Mr[Q - 1])));
-                s16x2 gI = as_s16x2(shift_in(s16_bits(Ir[Q - 1])));
-                s16x2 gD = as_s16x2(shift_in(s16_bits(Dr[Q - 1])));
+                // This row's N, and a floor under the next row's B->M score
+                // (B is at least N + move).  A D value d can raise a cell of
+                // the next row only through D->M, by at most d + maxdm, while
+                // every such cell is at least that floor: D values below thr
+                // cannot change any M of the next row, hence no E and no
+                // score (D feeds nothing else).  Rows past the sequence's end
+                // need none.
+                const int nN = sat16(xN + loop);
+                const int bclo = sat16(sat16(nN + move) + a.tbm);
+                const int t1 = bclo - maxdm - 1;
+                const s16x2 thr1 = splat16(live ? (t1 > kP7Pos ? kP7Pos : (t1 < kP7Neg ? kP7Neg : t1))
+                                                : kP7Pos);
+                // ---- M and I, registers in descending order ----------------
+                // (in place: slot q's new M reads the old M, I and D of slot
+                // q - 1, not yet overwritten; its new I reads its own old M
+                // and I, updated first).  Slot 0 of each element reads the
+                // previous element's last slot, shifted in before the pass.
+                const s16x2 sM = as_s16x2(shift_in(s16_bits(Mr[Q - 1])));
+                const s16x2 sI = as_s16x2(shift_in(s16_bits(Ir[Q - 1])));
+                const s16x2 sD = as_s16x2(shift_in(s16_bits(Dr[Q - 1])));
                 s16x2 xe = neg;
-                uint32_t md0 = 0u;
-                // register q from its dwords of the 8 rows (emission, then
-                // MMp, IMp, DMp, MI, II, MDp, DDp)
-                auto cell = [&](int q, uint32_t e, uint32_t mm, uint32_t im, uint32_t dm,
-                                uint32_t mi, uint32_t ii, uint32_t md, uint32_t dd) {
-                    const s16x2 oM = Mr[q], oI = Ir[q], oD = Dr[q];
+                auto mi_cell = [&](int q, uint32_t e, uint32_t mm, uint32_t im, uint32_t dm,
+                                   uint32_t mi, uint32_t ii) {
+                    const s16x2 gM = q > 0 ? Mr[q - 1] : sM;
+                    const s16x2 gI = q > 0 ? Ir[q - 1] : sI;
+                    const s16x2 gD = q > 0 ? Dr[q - 1] : sD;
+                    // (pinned here: left to itself the compiler sinks the I
+                    // update to the row's end and keeps copies of the old M)
+                    s16x2 nI = smax(adds(Mr[q], as_s16x2(mi)), adds(Ir[q], as_s16x2(ii)));
+                    asm volatile("" : "+v"(nI));
+                    Ir[q] = nI;
                     const s16x2 c = smax(smax(adds(gM, as_s16x2(mm)), adds(gI, as_s16x2(im))),
                                          smax(adds(gD, as_s16x2(dm)), bc));
                     Mr[q] = adds(c, as_s16x2(e));
-                    Ir[q] = smax(adds(oM, as_s16x2(mi)), adds(oI, as_s16x2(ii)));
-                    Dr[q] = q == 0 ? neg
-                                   : smax(adds(Mr[q - 1], as_s16x2(md)),
-                                          adds(Dr[q - 1], as_s16x2(dd)));
-                    if (q == 0) md0 = md;
                     xe = smax(xe, Mr[q]);
-                    gM = oM;
-                    gI = oI;
-                    gD = oD;
                 };
-#pragma unroll
-                for (int ch = 0; ch < Lay::NF; ++ch) {
-                    // one chunk's 32 score dwords at a time: keeps the
-                    // scheduler from hoisting every chunk's loads at once
-                    __builtin_amdgcn_sched_barrier(0);
-                    const uint4 ve = chunk(x, ch), vmm = chunk(rT + kP7MMp, ch),
-                                vim = chunk(rT + kP7IMp, ch), vdm = chunk(rT + kP7DMp, ch),
-                                vmi = chunk(rT + kP7MI, ch), vii = chunk(rT + kP7II, ch),
-                                vmd = chunk(rT + kP7MDp, ch), vdd = chunk(rT + kP7DDp, ch);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        if (ch * 4 + u < Q)
-                            cell(ch * 4 + u, comp(ve, u), comp(vmm, u), comp(vim, u),
-                                 comp(vdm, u), comp(vmi, u), comp(vii, u), comp(vmd, u),
-                                 comp(vdd, u));
-                    }
+                if constexpr (Lay::T1) {
+                    mi_cell(Lay::Q1, tail1(x), tail1(rT + kP7MMp), tail1(rT + kP7IMp),
+                            tail1(rT + kP7DMp), tail1(rT + kP7MI), tail1(rT + kP7II));
                 }
                 if constexpr (Lay::T2) {
                     const uint2 ve = tail2(x), vmm = tail2(rT + kP7MMp), vim = tail2(rT + kP7IMp),
                                 vdm = tail2(rT + kP7DMp), vmi = tail2(rT + kP7MI),
-                                vii = tail2(rT + kP7II), vmd = tail2(rT + kP7MDp),
-                                vdd = tail2(rT + kP7DDp);
-                    cell(Lay::Q2, ve.x, vmm.x, vim.x, vdm.x, vmi.x, vii.x, vmd.x, vdd.x);
-                    cell(Lay::Q2 + 1, ve.y, vmm.y, vim.y, vdm.y, vmi.y, vii.y, vmd.y, vdd.y);
+                                vii = tail2(rT + kP7II);
+                    mi_cell(Lay::Q2 + 1, ve.y, vmm.y, vim.y, vdm.y, vmi.y, vii.y);
+                    mi_cell(Lay::Q2, ve.x, vmm.x, vim.x, vdm.x, vmi.x, vii.x);
                 }
-                if constexpr (Lay::T1) {
-                    cell(Lay::Q1, tail1(x), tail1(rT + kP7MMp), tail1(rT + kP7IMp),
-                         tail1(rT + kP7DMp), tail1(rT + kP7MI), tail1(rT + kP7II),
-                         tail1(rT + kP7MDp), tail1(rT + kP7DDp));
+#pragma unroll
+                for (int ch = Lay::NF - 1; ch >= 0; --ch) {
+                    // one chunk's 24 score dwords at a time: keeps the
+                    // scheduler from hoisting every chunk's loads at once
+                    __builtin_amdgcn_sched_barrier(0);
+                    const uint4 ve = chunk(x, ch), vmm = chunk(rT + kP7MMp, ch),
+                                vim = chunk(rT + kP7IMp, ch), vdm = chunk(rT + kP7DMp, ch),
+                                vmi = chunk(rT + kP7MI, ch), vii = chunk(rT + kP7II, ch);
+#pragma unroll
+                    for (int u = 3; u >= 0; --u) {
+                        if (ch * 4 + u < Q)
+                            mi_cell(ch * 4 + u, comp(ve, u), comp(vmm, u), comp(vim, u),
+                                    comp(vdm, u), comp(vmi, u), comp(vii, u));
+                    }
                 }
-                // ---- D chains across elements (lazy F) --------------------
-                // each element's first slot takes the previous element's last
+                // ---- D within each element, ascending ----------------------
+                // (from the new M; slot 0's D waits for the chain below)
+                uint32_t md0 = 0u, dd0 = 0u;
+                auto d_cell = [&](int q, uint32_t md, uint32_t dd) {
+                    if (q == 0) {
+                        Dr[0] = neg;
+                        md0 = md;
+                        dd0 = dd;
+                    } else {
+                        Dr[q] = smax(adds(Mr[q - 1], as_s16x2(md)), adds(Dr[q - 1], as_s16x2(dd)));
+                    }
+                };
+#pragma unroll
+                for (int ch = 0; ch < Lay::NF; ++ch) {
+                    const uint4 vmd = chunk(rT + kP7MDp, ch), vdd = chunk(rT + kP7DDp, ch);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (ch * 4 + u < Q) d_cell(ch * 4 + u, comp(vmd, u), comp(vdd, u));
+                }
+                if constexpr (Lay::T2) {
+                    const uint2 vmd = tail2(rT + kP7MDp), vdd = tail2(rT + kP7DDp);
+                    d_cell(Lay::Q2, vmd.x, vdd.x);
+                    d_cell(Lay::Q2 + 1, vmd.y, vdd.y);
+                }
+                if constexpr (Lay::T1) d_cell(Lay::Q1, tail1(rT + kP7MDp), tail1(rT + kP7DDp));
+                // ---- D chains across elements, where they matter ----------
+                // Each element's first slot takes the previous element's last
                 // M (through M->D) and last D (through D->D), carried along
-                // its slots, until no element's last D changes
+                // its slots; passes repeat while some element's last D rose
+                // to a value that matters (at least thr).  Values that do not
+                // matter may stay below the sequential chain's.
                 const s16x2 cinM = adds(as_s16x2(shift_in(s16_bits(Mr[Q - 1]))), as_s16x2(md0));
-                for (;;) {
-                    const uint32_t last = s16_bits(Dr[Q - 1]);
-                    s16x2 carry = as_s16x2(shift_in(last));
+                s16x2 in0 = smax(cinM, adds(as_s16x2(shift_in(s16_bits(Dr[Q - 1]))),
+                                            as_s16x2(dd0)));
+                s16x2 lim = smax(Dr[0], thr1);
+                bool more = __any(s16_bits(smax(in0, lim)) != s16_bits(lim));
+                while (more) {
+                    const s16x2 last = Dr[Q - 1];
+                    Dr[0] = smax(Dr[0], in0);
                     auto link = [&](int q, uint32_t dd) {
-                        const s16x2 c = q == 0 ? smax(cinM, adds(carry, as_s16x2(dd)))
-                                               : adds(Dr[q - 1], as_s16x2(dd));
-                        Dr[q] = smax(Dr[q], c);
+                        if (q > 0) Dr[q] = smax(Dr[q], adds(Dr[q - 1], as_s16x2(dd)));
                     };
 #pragma unroll
                     for (int ch = 0; ch < Lay::NF; ++ch) {
@@ -298,20 +358,24 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
                         link(Lay::Q2 + 1, vdd.y);
                     }
                     if constexpr (Lay::T1) link(Lay::Q1, tail1(rT + kP7DDp));
-                    if (!__any(s16_bits(Dr[Q - 1]) != last)) break;
+                    lim = smax(last, thr1);
+                    more = __any(s16_bits(smax(Dr[Q - 1], lim)) != s16_bits(lim));
+                    in0 = smax(cinM, adds(as_s16x2(shift_in(s16_bits(Dr[Q - 1]))),
+                                          as_s16x2(dd0)));
                 }
                 // ---- special states (Plan-7 N, B, E, C, J) ----------------
                 const int eh = (int)xe.x > (int)xe.y ? (int)xe.x : (int)xe.y;
                 const int E = group_max<G>(eh);
                 if (live) {
                     if (E >= kP7Pos) ovf = true;
-                    const int j1 = sat16(xJ + loop), j2 = sat16(E + kP7Half);
-                    xJ = j1 > j2 ? j1 : j2;
-                    const int c1 = sat16(xC + loop), c2 = sat16(E + kP7Half);
-                    xC = c1 > c2 ? c1 : c2;
-                    xN = sat16(xN + loop);
-                    const int b1 = sat16(xN + move), b2 = sat16(xJ + move);
-                    xB = b1 > b2 ? b1 : b2;
+                    const int e2 = sat16(E + kP7Half);
+                    const int j1 = sat16(xJ + loop), c1 = sat16(xC + loop);
+                    xJ = j1 > e2 ? j1 : e2;
+                    xC = c1 > e2 ? c1 : e2;
+                    xN = nN;
+                    // max(N + move, J + move) = max(N, J) + move (saturation
+                    // is monotone)
+                    xB = sat16((xN > xJ ? xN : xJ) + move);
                 }
             }
             done += 16;
@@ -327,9 +391,10 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
             a.score[id] = ovf ? (int16_t)kP7Pos : (int16_t)sat16(xC + move);
             a.flag[id] = ovf ? 1 : 0;
         }
+        const int claimed = claim(ended);
         if (ended) {
-            ++k;
-            t = record_of(k);
+            t = tn;
+            tn = claimed;
             rec = nrec;
             rec16 = nrec16;
             lm = nlm;
@@ -349,7 +414,8 @@ hipError_t launch_p7(const P7Args &a, int wpb, int blocks, hipStream_t s) {
     if (a.rows != kRows && a.rows != kDegenRows) return hipErrorInvalidValue;
     const int n = (a.rows + 7) * lds_layout(G, Q, kP7Rows).RS;
     if (wpb < 1 || wpb > kP7MaxWaves) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((p7_prep_kernel<G, Q>), dim3((n + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((p7_prep_kernel<G, Q>), dim3((n + 255) / 256 + 1), dim3(256), 0, s, a,
+                       (n + 255) / 256);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = p7_lds_bytes(G, Q, a.rows);

@@ -79,18 +79,23 @@ def test_p7_score_rejects_bad_arguments_before_launch():
                                  None) == -5
 
 
+TUNED = {30: (16, 8), 64: (8, 8), 100: (8, 8), 200: (8, 4), 400: (16, 4), 700: (32, 8),
+         1000: (32, 8), 1500: (64, 8), 2047: (64, 8), 2400: (64, 8), 2815: (64, 8)}
+
+
 def test_p7_default_plans_cover_every_length():
-    prev = 0
+    import math
     for M in list(range(1, 300)) + list(range(300, 2816, 29)) + [2815]:
         p = hm.p7_default_plan(M)
         assert 2 * p.G * p.Q - 1 >= M and 64 % p.G == 0, M
+        assert p.Q == -(-(M + 1) // (2 * p.G))          # the fewest registers
         assert p.Q <= (22 if p.G == 64 else 16)
         assert 0 < hm.p7_lds_bytes(p.G, p.Q) <= 160 * 1024
-        # the narrowest group that holds the profile
-        assert p.G >= prev
-        prev = p.G
-        if p.G > 4:
-            assert 2 * (p.G // 2) * 16 - 1 < M
+        # the nearest measured bin's plan where its group holds the profile
+        b = min(TUNED, key=lambda v: (abs(math.log(v) - math.log(M)), v))
+        G, wpb = TUNED[b]
+        if -(-(M + 1) // (2 * G)) <= (22 if G == 64 else 16):
+            assert (p.G, p.waves_per_block) == (G, wpb), (M, b)
     with pytest.raises(hm.HmsvError):
         hm.p7_default_plan(2816)
 

@@ -38,6 +38,17 @@ I8  with scB fixed, relative cells follow one recurrence whatever scB is,
     the rows from `warm` >= M - 1 before the first loud step to the end of
     the last one, with fresh cells, gives the exact score (before the first
     loud step scB never moved; after the last one nothing can change).
+
+and, for P7Viterbi (Eq. 1), on the striped layout of 2G elements of Q
+slots with a dummy slot 0:
+
+I9  a D value of row i reaches later results only through D->M into row
+    i + 1, where every cell also takes the B->M score; since B >= N + move,
+    a D value d with d + max_k tDM_k below sat(sat(N_i + move) + tBM) can
+    change no M, no E and no score.  So the D chains need completing across
+    elements (Farrar's lazy passes) only while some element's last D rises
+    to at least that threshold, and not at all in rows past the sequence's
+    end; the dummy slot may hold any value (all its transitions are -inf).
 """
 import numpy as np
 
@@ -598,3 +609,114 @@ def test_msv_windowed_rescore_matches_oracle():
             regimes["ovf" if exp[1] else ("j" if exp[0] > q.BASE else "plain")] += 1
     assert min(regimes.values()) > 3, regimes
     assert short_end > 0 and short_warm > 0, (short_end, short_warm)
+
+
+# ---------------------------------------------------------------- P7Viterbi
+
+def model_p7_striped(prof, x, G, Q, junk_rng):
+    """The P7 kernel's row update on the striped layout (slot s = q + Q e,
+    element e = 2 lane + half, slot 0 a dummy node) with the thresholded
+    lazy completion of the D chains (I9).  The dummy slot's diagonal
+    inputs come from another group (random values here).  Returns (score,
+    flag, rows that ran a lazy pass)."""
+    from oracle import p7 as op7
+    NEG, POS = -32768, 32767
+
+    def sat(v):
+        return np.clip(v, NEG, POS)
+
+    M, msc, tr, tbm = prof["M"], prof["msc"].astype(np.int64), prof["trans"].astype(np.int64), \
+        prof["tbm"]
+    E2 = 2 * G
+    assert 2 * G * Q - 1 >= M
+    slot = np.arange(E2 * Q).reshape(E2, Q)           # [e, q] -> s = q + Q e
+
+    def by_node(row, frm):
+        n = slot if frm == "self" else slot - 1
+        ok = (n >= 1) & (n <= M)
+        return np.where(ok, row[np.clip(n - 1, 0, M - 1)], NEG)
+
+    MM, MI, MD, IM, II, DM, DD = (by_node(tr[t], "self" if t in (1, 4) else "prev")
+                                  for t in range(7))
+    real = (slot >= 1) & (slot <= M)
+    maxdm = int(tr[5].max())
+    L = len(x)
+    lm = op7.length_model(L)
+    loop, move = lm["NN"], lm["NB"]
+    Mr = np.full((E2, Q), NEG)
+    Ir = Mr.copy()
+    Dr = Mr.copy()
+    xN, xB, xJ, xC, ovf, lazy_rows = 0, sat(move), NEG, NEG, False, 0
+
+    def shift(a):
+        out = np.empty(E2, np.int64)
+        out[1:] = a[:-1]
+        out[0] = junk_rng.integers(NEG, POS + 1)
+        return out
+
+    for i in range(L):
+        em = np.where(real, msc[x[i]][np.clip(slot - 1, 0, M - 1)], NEG)
+        bc = sat(xB + tbm)
+        nN = sat(xN + loop)
+        thr1 = int(np.clip(sat(sat(nN + move) + tbm) - maxdm - 1, NEG, POS))
+        gM = np.concatenate([shift(Mr[:, Q - 1])[:, None], Mr[:, :-1]], axis=1)
+        gI = np.concatenate([shift(Ir[:, Q - 1])[:, None], Ir[:, :-1]], axis=1)
+        gD = np.concatenate([shift(Dr[:, Q - 1])[:, None], Dr[:, :-1]], axis=1)
+        Ir = np.maximum(sat(Mr + MI), sat(Ir + II))
+        c = np.maximum(np.maximum(sat(gM + MM), sat(gI + IM)), np.maximum(sat(gD + DM), bc))
+        Mr = sat(c + em)
+        Dr = np.full((E2, Q), NEG)
+        for q in range(1, Q):
+            Dr[:, q] = np.maximum(sat(Mr[:, q - 1] + MD[:, q]), sat(Dr[:, q - 1] + DD[:, q]))
+        cinM = sat(shift(Mr[:, Q - 1]) + MD[:, 0])
+        in0 = np.maximum(cinM, sat(shift(Dr[:, Q - 1]) + DD[:, 0]))
+        lim = np.maximum(Dr[:, 0], thr1)
+        more = bool((in0 > lim).any())
+        lazy_rows += more
+        while more:
+            last = Dr[:, Q - 1].copy()
+            Dr[:, 0] = np.maximum(Dr[:, 0], in0)
+            for q in range(1, Q):
+                Dr[:, q] = np.maximum(Dr[:, q], sat(Dr[:, q - 1] + DD[:, q]))
+            more = bool((Dr[:, Q - 1] > np.maximum(last, thr1)).any())
+            in0 = np.maximum(cinM, sat(shift(Dr[:, Q - 1]) + DD[:, 0]))
+        Ev = int(Mr.max())
+        if Ev >= POS:
+            ovf = True
+        e2 = sat(Ev - 32)
+        xJ = max(sat(xJ + loop), e2)
+        xC = max(sat(xC + loop), e2)
+        xN = nN
+        xB = sat(max(xN, xJ) + move)
+    return (POS if ovf else int(sat(xC + move))), int(ovf), lazy_rows
+
+
+def test_p7_thresholded_lazy_passes_match_oracle():
+    """I9 on random profiles (some with -inf transitions and emissions),
+    targets with gapped implants, several striped shapes: the model's
+    scores equal the oracle's, rows with and without lazy passes occur."""
+    from oracle import p7 as op7
+    rng = np.random.default_rng(909)
+    lazy = rows = 0
+    for trial in range(24):
+        M = int(rng.integers(1, 60))
+        G = int(rng.choice([1, 2, 4, 8]))
+        Q = max(1, -(-(M + 1) // (2 * G))) + int(rng.integers(0, 2))
+        e = synth.sample_emissions(rng, M, conc=0.5 if trial % 3 else 5.0)
+        t = synth.sample_transitions(rng, M, conc=20.0 if trial % 2 else 2.0)
+        if trial % 4 == 3:
+            t[rng.random(t.shape) < 0.1] = 0.0
+            e[rng.random(e.shape) < 0.05] = 0.0
+            e[:, 0] += 1e-3
+        prof = op7.quantize(e, t, synth.BG)
+        L = rng.integers(0, 90, size=6)
+        res, off = synth.sample_residues(rng, L.astype(np.int64))
+        synth.implant_gapped(rng, res, off, e, t, 0.7)
+        for k in range(len(L)):
+            xk = res[off[k]:off[k + 1]]
+            got = model_p7_striped(prof, xk, G, Q, rng)
+            assert got[:2] == oracle.p7_seq(prof, xk), (trial, M, G, Q, k)
+            lazy += got[2]
+            rows += len(xk)
+    assert 0 < lazy < rows, (lazy, rows)
+
