@@ -125,7 +125,8 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
 
 
 def resources(jobs: int | None = None) -> str:
-    """Compiler resource usage of the tuned plans' filter kernels, as a
+    """Compiler resource usage of the tuned plans' filter kernels (and the
+    exact pass and the default P7Viterbi plans), as a
     markdown table: VGPRs, SGPRs, scratch and the occupancy the compiler
     reports, the LDS image, and the wavefronts per SIMD the launch gets
     (VGPRs, LDS and waves per block together).  Compiles the kernel units
@@ -207,6 +208,47 @@ def resources(jobs: int | None = None) -> str:
         lines.append(f"| {qx} | {128 * qx - 1} | {u.get('VGPRs')} | {u.get('TotalSGPRs')} | "
                      f"{u.get('ScratchSize [bytes/lane]')} | {u.get('Occupancy [waves/SIMD]')} | "
                      f"{plan_lds_bytes(64, qx) / 1024:.1f} |")
+    # P7Viterbi: the default plans at the measured profile lengths
+    from paper_1707_09683_amd import p7_default_plan, p7_lds_bytes
+    p7_bins = (30, 64, 100, 200, 400, 700, 1000, 1100, 1500, 2047, 2400, 2815)
+    p7_plans = {}
+    for M in p7_bins:
+        pl = p7_default_plan(M)
+        p7_plans.setdefault((pl.G, pl.Q, pl.waves_per_block), []).append(M)
+
+    def p7_unit(gq):
+        G, Q = gq
+        with tempfile.TemporaryDirectory() as td:
+            cmd = [HIPCC, *COMMON, f"-DHMSV_G={G}", f"-DHMSV_QLO={Q}", f"-DHMSV_QHI={Q}",
+                   "--cuda-device-only", "-c", os.path.join(CSRC, "p7.hip"),
+                   "-o", os.path.join(td, "p.o"), "-Rpass-analysis=kernel-resource-usage"]
+            return gq, subprocess.run(cmd, capture_output=True, text=True).stderr
+
+    p7_use = {}
+    with cf.ThreadPoolExecutor(max_workers=jobs or 8) as ex:
+        for (G, Q), err in ex.map(p7_unit, sorted({(g, q) for g, q, _w in p7_plans})):
+            cur = None
+            for m in rx.finditer(err):
+                k, v = m.group(1), m.group(2)
+                if k == "Function Name":
+                    cur = (G, Q) if re.search(r"p7_kernelILi\d+ELi\d+ELi\d+E", v) else None
+                    if cur:
+                        p7_use[cur] = {}
+                elif cur:
+                    p7_use[cur][k] = int(v)
+    lines += ["", "P7Viterbi (`p7_kernel<G, Q, threads>`, default plans at the measured lengths; "
+              "blocks of 16 wavefronts are 1024-thread kernels):",
+              "", "| M-bins | G | Q | waves/block | VGPRs | SGPRs | scratch B/lane | "
+              "waves/SIMD (VGPRs) | LDS KiB/block | waves/SIMD (launch) |",
+              "|---|---|---|---|---|---|---|---|---|---|"]
+    for (G, Q, wpb), Ms in sorted(p7_plans.items(), key=lambda t: min(t[1])):
+        u = p7_use.get((G, Q), {})
+        lds = p7_lds_bytes(G, Q)
+        occ_v = u.get("Occupancy [waves/SIMD]", 0)
+        blocks = min(160 * 1024 // lds, (4 * occ_v) // wpb) if lds else 0
+        lines.append(f"| {','.join(map(str, Ms))} | {G} | {Q} | {wpb} | {u.get('VGPRs')} | "
+                     f"{u.get('TotalSGPRs')} | {u.get('ScratchSize [bytes/lane]')} | {occ_v} | "
+                     f"{lds / 1024:.1f} | {blocks * wpb / 4:g} |")
     return "\n".join(lines)
 
 

@@ -959,8 +959,9 @@ struct P7Tuned {
     int bin, G, wpb;
 };
 constexpr P7Tuned kP7Tuned[] = {
-    {30, 16, 8},  {64, 8, 8},   {100, 8, 8},  {200, 8, 4},   {400, 16, 4},  {700, 32, 8},
-    {1000, 32, 8}, {1500, 64, 8}, {2047, 64, 8}, {2400, 64, 8}, {2815, 64, 8},
+    {30, 16, 8},    {64, 8, 8},     {100, 8, 8},    {200, 8, 4},    {400, 16, 4},
+    {700, 32, 8},   {1000, 32, 8},  {1100, 64, 16}, {1500, 64, 16}, {2047, 64, 16},
+    {2400, 64, 8},  {2815, 64, 8},
 };
 
 hmsv_status hmsv_p7_default_plan(int32_t M, hmsv_plan *plan) {
@@ -1029,7 +1030,7 @@ hmsv_status hmsv_p7_score(const hmsv_p7_profile *prof, const hmsv_db *db, int16_
     }
     if (plan.G < 1 || plan.G > 64 || (64 % plan.G) != 0 || plan.Q < 1 ||
         plan_nodes(plan.G, plan.Q) < prof->M || plan.blocks < 0 ||
-        plan.waves_per_block < 1 || plan.waves_per_block > 8)
+        plan.waves_per_block < 1 || plan.waves_per_block > ((plan.G == 64 && plan.Q <= 16) ? 16 : 8))
         return HMSV_EINVAL;
     const P7KernelEntry *e = registry().find_p7(plan.G, plan.Q);
     if (!e) return HMSV_ENOKERNEL;

@@ -404,43 +404,63 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     }
 }
 
-// At most 8 wavefronts per block: with 1024 threads the compiler caps the
-// kernel at 128 VGPRs and spills the cell registers of the wider plans.
-constexpr int kP7MaxWaves = 8;
+// Blocks of up to 8 wavefronts (512 threads), or 16 for 64-lane groups of
+// at most 16 registers: their LDS image allows one block per CU, and these
+// stay within the 128 VGPRs a 1024-thread block leaves (wider plans would
+// spill their cell registers).
+template <int G, int Q>
+constexpr int kP7MaxWaves = (G == 64 && Q <= 16) ? 16 : 8;
+
+template <int G, int Q, int THREADS>
+hipError_t launch_p7_kernel(const P7Args &a, int wpb, int blocks, hipStream_t s) {
+    const size_t lds = p7_lds_bytes(G, Q, a.rows);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)p7_kernel<G, Q, THREADS>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((p7_kernel<G, Q, THREADS>), dim3(blocks), dim3(wpb * 64), lds, s, a);
+    return hipGetLastError();
+}
 
 // The LDS image, then the filter kernel.
 template <int G, int Q>
 hipError_t launch_p7(const P7Args &a, int wpb, int blocks, hipStream_t s) {
     if (a.rows != kRows && a.rows != kDegenRows) return hipErrorInvalidValue;
     const int n = (a.rows + 7) * lds_layout(G, Q, kP7Rows).RS;
-    if (wpb < 1 || wpb > kP7MaxWaves) return hipErrorInvalidValue;
+    if (wpb < 1 || wpb > kP7MaxWaves<G, Q>) return hipErrorInvalidValue;
     hipLaunchKernelGGL((p7_prep_kernel<G, Q>), dim3((n + 255) / 256 + 1), dim3(256), 0, s, a,
                        (n + 255) / 256);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds = p7_lds_bytes(G, Q, a.rows);
-    if (lds > 64 * 1024) {
-        e = hipFuncSetAttribute((const void *)p7_kernel<G, Q, 512>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
+    if constexpr (kP7MaxWaves<G, Q> > 8) {
+        if (wpb > 8) return launch_p7_kernel<G, Q, 1024>(a, wpb, blocks, s);
     }
-    hipLaunchKernelGGL((p7_kernel<G, Q, 512>), dim3(blocks), dim3(wpb * 64), lds, s, a);
-    return hipGetLastError();
+    return launch_p7_kernel<G, Q, 512>(a, wpb, blocks, s);
 }
 
-// Resident blocks of wpb wavefronts per CU (0 on error).
-template <int G, int Q>
-int occupancy_p7(int wpb, int rows) {
-    if (wpb < 1 || wpb > kP7MaxWaves) return 0;
+template <int G, int Q, int THREADS>
+int occupancy_p7_kernel(int wpb, int rows) {
     int nb = 0;
     const size_t lds = p7_lds_bytes(G, Q, rows);
-    if (hipFuncSetAttribute((const void *)p7_kernel<G, Q, 512>,
+    if (hipFuncSetAttribute((const void *)p7_kernel<G, Q, THREADS>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, p7_kernel<G, Q, 512>, wpb * 64,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, p7_kernel<G, Q, THREADS>, wpb * 64,
                                                      lds) != hipSuccess)
         return 0;
     return nb;
+}
+
+// Resident blocks of wpb wavefronts per CU (0 on error or an unsupported
+// block size).
+template <int G, int Q>
+int occupancy_p7(int wpb, int rows) {
+    if (wpb < 1 || wpb > kP7MaxWaves<G, Q>) return 0;
+    if constexpr (kP7MaxWaves<G, Q> > 8) {
+        if (wpb > 8) return occupancy_p7_kernel<G, Q, 1024>(wpb, rows);
+    }
+    return occupancy_p7_kernel<G, Q, 512>(wpb, rows);
 }
 
 }  // namespace hmsv

@@ -80,7 +80,8 @@ def test_p7_score_rejects_bad_arguments_before_launch():
 
 
 TUNED = {30: (16, 8), 64: (8, 8), 100: (8, 8), 200: (8, 4), 400: (16, 4), 700: (32, 8),
-         1000: (32, 8), 1500: (64, 8), 2047: (64, 8), 2400: (64, 8), 2815: (64, 8)}
+         1000: (32, 8), 1100: (64, 16), 1500: (64, 16), 2047: (64, 16), 2400: (64, 8),
+         2815: (64, 8)}
 
 
 def test_p7_default_plans_cover_every_length():

@@ -181,3 +181,15 @@ def test_p7_repeat_calls_share_workspace(hm):
     _check((s1.cpu().numpy(), f1.cpu().numpy()), _oracle(e1, t1, res, off), "first")
     _check((s2.cpu().numpy(), f2.cpu().numpy()), _oracle(e2, t2, res, off), "second")
     db.close()
+
+
+@pytest.mark.parametrize("Q,M", [(2, 200), (16, 2047)])
+def test_p7_sixteen_wave_blocks(hm, Q, M):
+    """64-lane groups of at most 16 registers also run as blocks of 16
+    wavefronts (1024 threads)."""
+    e, t = _profile(71 + M, M)
+    res, off = _db(72 + M, M, e, t, 600, 0, 900, frac=0.3)
+    print(f"case p7 16-wave blocks Q={Q} M={M}", flush=True)
+    exp = _oracle(e, t, res, off)
+    for wpb in (16, 12):
+        _check(_run(hm, e, t, res, off, hm.make_plan(64, Q, wpb)), exp, f"wpb={wpb} Q={Q}")
