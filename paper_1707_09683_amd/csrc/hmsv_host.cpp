@@ -959,7 +959,7 @@ struct P7Tuned {
     int bin, G, wpb;
 };
 constexpr P7Tuned kP7Tuned[] = {
-    {30, 16, 8},    {64, 8, 8},     {100, 8, 8},    {200, 8, 4},    {400, 16, 4},
+    {30, 8, 4},     {64, 8, 4},     {100, 8, 8},    {200, 8, 4},    {400, 16, 4},
     {700, 32, 8},   {1000, 32, 8},  {1100, 64, 16}, {1500, 64, 16}, {2047, 64, 16},
     {2400, 64, 8},  {2815, 64, 8},
 };
@@ -1061,7 +1061,8 @@ hmsv_status hmsv_p7_score(const hmsv_p7_profile *prof, const hmsv_db *db, int16_
     a.pad_off = db->pad_off;
     a.score = score;
     a.flag = flags;
-    a.image = (uint32_t *)((char *)workspace + kWsCounterBytes);
+    a.image = (uint32_t *)((char *)workspace + kWsP7ImageOff);
+    a.queue = (uint32_t *)((char *)workspace + kWsP7QueueOff);
     a.aux = (int32_t *)workspace;
     a.rows = db->table_rows;
     if (e->launch(a, plan.waves_per_block, blocks, stream) != hipSuccess) return HMSV_EDEVICE;

@@ -192,13 +192,20 @@ struct P7Args {
     int16_t *score;
     uint8_t *flag;
     uint32_t *image;       // the LDS image (workspace)
-    int32_t *aux;          // workspace words: [0] max over nodes of D->M, [1] the
-                           // record queue (both set by the prep kernel)
+    int32_t *aux;          // workspace word: max over nodes of D->M (prep kernel)
+    uint32_t *queue;       // kP7Parts record queues, 128 bytes apart (zeroed by the
+                           // prep kernel)
     int32_t rows;          // emission rows (kRows or kDegenRows); the 7
                            // transition rows follow them
 };
 
 constexpr int kMaxP7G = 64;
+constexpr int kP7Parts = 16;                 // record queues of a P7 call
+// P7 calls' workspace: aux word at 0, the queues from kWsCounterBytes, the
+// LDS image after them (P7 uses none of the MSV/SSV regions).
+constexpr size_t kWsP7QueueOff = kWsCounterBytes;
+constexpr size_t kWsP7ImageOff = kWsP7QueueOff + (size_t)kP7Parts * 128;
+static_assert(kWsP7ImageOff + 160 * 1024 <= kWsWinOff, "P7 image within the workspace");
 typedef hipError_t (*P7LaunchFn)(const P7Args &, int waves_per_block, int blocks, hipStream_t);
 struct P7KernelEntry {
     int G;

@@ -30,8 +30,9 @@
 // image's conflict-free layout.
 // The special states are updated once per row from the group's maximum.
 //
-// Lane groups take records (longest first) from a queue as they finish
-// one; the next record is claimed and loaded while the current one runs.  A sequence runs exactly L rows: the rows of the last
+// Lane groups take records (longest first) from queues as they finish one;
+// the next record is loaded, and the one after it claimed, while the
+// current one runs.  A sequence runs exactly L rows: the rows of the last
 // 16-residue step past L leave the special states untouched.
 #pragma once
 #include <utility>
@@ -90,10 +91,8 @@ __global__ void __launch_bounds__(256) p7_prep_kernel(P7Args a, int image_blocks
                 red[threadIdx.x] = red[threadIdx.x + h];
             __syncthreads();
         }
-        if (threadIdx.x == 0) {
-            a.aux[0] = red[0];
-            a.aux[1] = 0;               // the record queue
-        }
+        if (threadIdx.x == 0) a.aux[0] = red[0];
+        if (threadIdx.x < kP7Parts) a.queue[threadIdx.x * 32] = 0u;   // the record queues
         return;
     }
     const int idx = (int)(blockIdx.x * 256 + threadIdx.x);
@@ -166,20 +165,32 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     const uint32_t rT = (uint32_t)a.rows;    // first transition row
 
     const int nseq = a.nseq;
-    // Records come from a queue (a counter the prep kernel zeroed), longest
-    // first: a lane group claims its next record when it starts one, so a
-    // group that drew a long sequence draws fewer others.  `want`: the
-    // groups that claim (the whole wavefront takes part in the broadcast).
-    uint32_t *queue = (uint32_t *)(a.aux + 1);
-    auto claim = [&](bool want) -> int {
-        int v = 0;
-        if (want && gstart) v = (int)atomicAdd(queue, 1u);
-        if constexpr (G > 1) v = __shfl(v, lane - j);
-        return v;
+    // Records come from queues (counters the prep kernel zeroed), longest
+    // first: a lane group claims a record as it starts one, so a group that
+    // drew a long sequence draws fewer others.  Blocks are spread over up to
+    // kP7Parts queues, each on its own 128-byte line: queue p hands out
+    // records p, p + P, p + 2P, ... (each longest first), so one counter's
+    // atomics come from a fraction of the grid.  A claim is taken (its value
+    // broadcast from the group's first lane) only at the group's next
+    // switch, by when it has returned: `issue` for the groups that claim,
+    // `take` by the whole wavefront.
+    const int nparts = (int)(gridDim.x < (unsigned)kP7Parts ? gridDim.x : (unsigned)kP7Parts);
+    const int part = (int)(blockIdx.x % (unsigned)nparts);
+    uint32_t *ctr = a.queue + part * 32;
+    uint32_t craw = 0u;
+    auto issue = [&](bool want) {
+        if (want && gstart) craw = atomicAdd(ctr, 1u);
+    };
+    auto take = [&]() -> int {
+        int k = (int)craw;
+        if constexpr (G > 1) k = __shfl(k, lane - j);
+        const long long r = (long long)part + (long long)nparts * (long long)k;
+        return r < (long long)nseq ? (int)r : nseq;
     };
 
     s16x2 Mr[Q], Ir[Q], Dr[Q];
-    int t = claim(true);
+    issue(true);
+    int t = take();
     uint4 rec = make_uint4(0u, 0u, 0u, 0u), rec16 = rec;
     uint32_t lm = 0u;
     if (t < nseq) {
@@ -188,7 +199,8 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
         lm = a.lenmodel[t];
     }
     // the next record, claimed and loaded while the current one runs
-    int tn = claim(true);
+    issue(true);
+    int tn = take();
     uint4 nrec = rec, nrec16 = rec16;
     uint32_t nlm = lm;
     auto prefetch = [&]() {
@@ -227,6 +239,7 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     };
     start();
     prefetch();
+    issue(true);                 // the record after that, taken at the switch
 
     for (;;) {
         if (!__any(active)) break;
@@ -235,24 +248,27 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
             // residues of the next step (the database stores every sequence
             // in whole 16-residue steps plus 16 more bytes)
             const uint4 wn = *(const uint4 *)(a.res + off + 16u);
+            // The floor under the B->M score of the rows after this step's
+            // rows (B >= N + move, and N only falls: the loop score is <= 0,
+            // so N after the step's last row bounds every row of the step).
+            // A D value d can raise a cell of the next row only through
+            // D->M, to at most d + maxdm, while every such cell is at least
+            // that floor: D values below thr cannot change any M, hence no E
+            // and no score (D feeds nothing else).  A lower bound than the
+            // row's own is still a bound, so one per step serves its rows.
+            int thr_step;
+            {
+                const int nEnd = sat16(xN + 16 * loop);
+                const int t1 = sat16(sat16(nEnd + move) + a.tbm) - maxdm - 1;
+                thr_step = active ? (t1 > kP7Pos ? kP7Pos : (t1 < kP7Neg ? kP7Neg : t1)) : kP7Pos;
+            }
+            const s16x2 thr1 = splat16(thr_step);
 #pragma unroll 1
             for (int r = 0; r < 16; ++r) {
                 const uint32_t word = r < 4 ? wv.x : r < 8 ? wv.y : r < 12 ? wv.z : wv.w;
                 const uint32_t x = (word >> (8 * (r & 3))) & 0xffu;
                 const bool live = active && done + r < len;
                 const s16x2 bc = splat16(sat16(xB + a.tbm));
-                // This row's N, and a floor under the next row's B->M score
-                // (B is at least N + move).  A D value d can raise a cell of
-                // the next row only through D->M, by at most d + maxdm, while
-                // every such cell is at least that floor: D values below thr
-                // cannot change any M of the next row, hence no E and no
-                // score (D feeds nothing else).  Rows past the sequence's end
-                // need none.
-                const int nN = sat16(xN + loop);
-                const int bclo = sat16(sat16(nN + move) + a.tbm);
-                const int t1 = bclo - maxdm - 1;
-                const s16x2 thr1 = splat16(live ? (t1 > kP7Pos ? kP7Pos : (t1 < kP7Neg ? kP7Neg : t1))
-                                                : kP7Pos);
                 // ---- M and I, registers in descending order ----------------
                 // (in place: slot q's new M reads the old M, I and D of slot
                 // q - 1, not yet overwritten; its new I reads its own old M
@@ -372,7 +388,7 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
                     const int j1 = sat16(xJ + loop), c1 = sat16(xC + loop);
                     xJ = j1 > e2 ? j1 : e2;
                     xC = c1 > e2 ? c1 : e2;
-                    xN = nN;
+                    xN = sat16(xN + loop);
                     // max(N + move, J + move) = max(N, J) + move (saturation
                     // is monotone)
                     xB = sat16((xN > xJ ? xN : xJ) + move);
@@ -391,7 +407,7 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
             a.score[id] = ovf ? (int16_t)kP7Pos : (int16_t)sat16(xC + move);
             a.flag[id] = ovf ? 1 : 0;
         }
-        const int claimed = claim(ended);
+        const int claimed = take();
         if (ended) {
             t = tn;
             tn = claimed;
@@ -401,6 +417,7 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
             start();
             prefetch();
         }
+        issue(ended);
     }
 }
 

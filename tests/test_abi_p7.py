@@ -79,7 +79,7 @@ def test_p7_score_rejects_bad_arguments_before_launch():
                                  None) == -5
 
 
-TUNED = {30: (16, 8), 64: (8, 8), 100: (8, 8), 200: (8, 4), 400: (16, 4), 700: (32, 8),
+TUNED = {30: (8, 4), 64: (8, 4), 100: (8, 8), 200: (8, 4), 400: (16, 4), 700: (32, 8),
          1000: (32, 8), 1100: (64, 16), 1500: (64, 16), 2047: (64, 16), 2400: (64, 8),
          2815: (64, 8)}
 

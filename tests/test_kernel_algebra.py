@@ -47,8 +47,10 @@ I9  a D value of row i reaches later results only through D->M into row
     a D value d with d + max_k tDM_k below sat(sat(N_i + move) + tBM) can
     change no M, no E and no score.  So the D chains need completing across
     elements (Farrar's lazy passes) only while some element's last D rises
-    to at least that threshold, and not at all in rows past the sequence's
-    end; the dummy slot may hold any value (all its transitions are -inf).
+    to at least that threshold; any lower threshold is also safe, so the
+    kernel takes, for a whole 16-row step, the one of the step's last row
+    (N only falls).  The dummy slot may hold any value (all its
+    transitions are -inf).
 """
 import numpy as np
 
@@ -658,7 +660,10 @@ def model_p7_striped(prof, x, G, Q, junk_rng):
         em = np.where(real, msc[x[i]][np.clip(slot - 1, 0, M - 1)], NEG)
         bc = sat(xB + tbm)
         nN = sat(xN + loop)
-        thr1 = int(np.clip(sat(sat(nN + move) + tbm) - maxdm - 1, NEG, POS))
+        if i % 16 == 0:
+            # one bound per 16-row step: the step's last row's (N only falls)
+            thr1 = int(np.clip(sat(sat(sat(xN + 16 * loop) + move) + tbm) - maxdm - 1,
+                               NEG, POS))
         gM = np.concatenate([shift(Mr[:, Q - 1])[:, None], Mr[:, :-1]], axis=1)
         gI = np.concatenate([shift(Ir[:, Q - 1])[:, None], Ir[:, :-1]], axis=1)
         gD = np.concatenate([shift(Dr[:, Q - 1])[:, None], Dr[:, :-1]], axis=1)
