@@ -320,12 +320,13 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
                     }
                 }
                 // ---- D within each element, ascending ----------------------
-                // (from the new M; slot 0's D waits for the chain below)
-                uint32_t md0 = 0u, dd0 = 0u;
+                // (from the new M; slot 0 takes the previous element's last M
+                // through M->D here, its last D below)
+                const s16x2 sMn = as_s16x2(shift_in(s16_bits(Mr[Q - 1])));
+                uint32_t dd0 = 0u;
                 auto d_cell = [&](int q, uint32_t md, uint32_t dd) {
                     if (q == 0) {
-                        Dr[0] = neg;
-                        md0 = md;
+                        Dr[0] = adds(sMn, as_s16x2(md));
                         dd0 = dd;
                     } else {
                         Dr[q] = smax(adds(Mr[q - 1], as_s16x2(md)), adds(Dr[q - 1], as_s16x2(dd)));
@@ -346,13 +347,11 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
                 if constexpr (Lay::T1) d_cell(Lay::Q1, tail1(rT + kP7MDp), tail1(rT + kP7DDp));
                 // ---- D chains across elements, where they matter ----------
                 // Each element's first slot takes the previous element's last
-                // M (through M->D) and last D (through D->D), carried along
-                // its slots; passes repeat while some element's last D rose
-                // to a value that matters (at least thr).  Values that do not
-                // matter may stay below the sequential chain's.
-                const s16x2 cinM = adds(as_s16x2(shift_in(s16_bits(Mr[Q - 1]))), as_s16x2(md0));
-                s16x2 in0 = smax(cinM, adds(as_s16x2(shift_in(s16_bits(Dr[Q - 1]))),
-                                            as_s16x2(dd0)));
+                // D (through D->D), carried along its slots; passes repeat
+                // while some element's last D rose to a value that matters
+                // (at least thr).  Values that do not matter may stay below
+                // the sequential chain's.
+                s16x2 in0 = adds(as_s16x2(shift_in(s16_bits(Dr[Q - 1]))), as_s16x2(dd0));
                 s16x2 lim = smax(Dr[0], thr1);
                 bool more = __any(s16_bits(smax(in0, lim)) != s16_bits(lim));
                 while (more) {
@@ -376,8 +375,7 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
                     if constexpr (Lay::T1) link(Lay::Q1, tail1(rT + kP7DDp));
                     lim = smax(last, thr1);
                     more = __any(s16_bits(smax(Dr[Q - 1], lim)) != s16_bits(lim));
-                    in0 = smax(cinM, adds(as_s16x2(shift_in(s16_bits(Dr[Q - 1]))),
-                                          as_s16x2(dd0)));
+                    in0 = adds(as_s16x2(shift_in(s16_bits(Dr[Q - 1]))), as_s16x2(dd0));
                 }
                 // ---- special states (Plan-7 N, B, E, C, J) ----------------
                 const int eh = (int)xe.x > (int)xe.y ? (int)xe.x : (int)xe.y;

@@ -671,10 +671,11 @@ def model_p7_striped(prof, x, G, Q, junk_rng):
         c = np.maximum(np.maximum(sat(gM + MM), sat(gI + IM)), np.maximum(sat(gD + DM), bc))
         Mr = sat(c + em)
         Dr = np.full((E2, Q), NEG)
+        # slot 0 takes the previous element's last M in the first pass
+        Dr[:, 0] = sat(shift(Mr[:, Q - 1]) + MD[:, 0])
         for q in range(1, Q):
             Dr[:, q] = np.maximum(sat(Mr[:, q - 1] + MD[:, q]), sat(Dr[:, q - 1] + DD[:, q]))
-        cinM = sat(shift(Mr[:, Q - 1]) + MD[:, 0])
-        in0 = np.maximum(cinM, sat(shift(Dr[:, Q - 1]) + DD[:, 0]))
+        in0 = sat(shift(Dr[:, Q - 1]) + DD[:, 0])
         lim = np.maximum(Dr[:, 0], thr1)
         more = bool((in0 > lim).any())
         lazy_rows += more
@@ -684,7 +685,7 @@ def model_p7_striped(prof, x, G, Q, junk_rng):
             for q in range(1, Q):
                 Dr[:, q] = np.maximum(Dr[:, q], sat(Dr[:, q - 1] + DD[:, q]))
             more = bool((Dr[:, Q - 1] > np.maximum(last, thr1)).any())
-            in0 = np.maximum(cinM, sat(shift(Dr[:, Q - 1]) + DD[:, 0]))
+            in0 = sat(shift(Dr[:, Q - 1]) + DD[:, 0])
         Ev = int(Mr.max())
         if Ev >= POS:
             ovf = True
