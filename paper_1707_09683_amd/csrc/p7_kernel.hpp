@@ -215,7 +215,10 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     uint32_t off = a.pad_off, seq_off = a.pad_off, id = 0;
     int len = 0, done = 0;       // residues of the sequence, rows run so far
     int loop = 0, move = 0;      // length model: N/J/C loops, N/J->B and C->T
-    int xN = 0, xB = 0, xJ = kP7Neg, xC = kP7Neg;
+    // special states, packed: JC = (J, C); NB's low half N; Bv's low half B
+    s16x2 JC = splat16(kP7Neg), NN = splat16(0), Bv = splat16(0);
+    s16x2 loop2 = splat16(0), move2 = splat16(0);
+    const s16x2 tbm2 = splat16(a.tbm), half2 = splat16(kP7Half);
     bool ovf = false;
     uint4 wv = make_uint4(0u, 0u, 0u, 0u);   // this step's 16 residues
     const s16x2 neg = splat16(kP7Neg);
@@ -228,10 +231,11 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
         done = 0;
         loop = (int)(short)(lm & 0xffffu);
         move = (int)(short)(lm >> 16);
-        xN = 0;
-        xB = sat16(xN + move);
-        xJ = kP7Neg;
-        xC = kP7Neg;
+        loop2 = splat16(loop);
+        move2 = splat16(move);
+        NN = splat16(0);
+        Bv = adds(NN, move2);
+        JC = splat16(kP7Neg);
         ovf = false;
         wv = active ? rec16 : make_uint4(0x14141414u, 0x14141414u, 0x14141414u, 0x14141414u);
 #pragma unroll
@@ -258,7 +262,7 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
             // row's own is still a bound, so one per step serves its rows.
             int thr_step;
             {
-                const int nEnd = sat16(xN + 16 * loop);
+                const int nEnd = sat16((int)NN.x + 16 * loop);
                 const int t1 = sat16(sat16(nEnd + move) + a.tbm) - maxdm - 1;
                 thr_step = active ? (t1 > kP7Pos ? kP7Pos : (t1 < kP7Neg ? kP7Neg : t1)) : kP7Pos;
             }
@@ -266,9 +270,9 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
 #pragma unroll 1
             for (int r = 0; r < 16; ++r) {
                 const uint32_t word = r < 4 ? wv.x : r < 8 ? wv.y : r < 12 ? wv.z : wv.w;
-                const uint32_t x = (word >> (8 * (r & 3))) & 0xffu;
+                const uint32_t x = __builtin_amdgcn_ubfe(word, 8u * (uint32_t)(r & 3), 8u);
                 const bool live = active && done + r < len;
-                const s16x2 bc = splat16(sat16(xB + a.tbm));
+                const s16x2 bc = adds(__builtin_shufflevector(Bv, Bv, 0, 0), tbm2);
                 // ---- M and I, registers in descending order ----------------
                 // (in place: slot q's new M reads the old M, I and D of slot
                 // q - 1, not yet overwritten; its new I reads its own old M
@@ -382,14 +386,12 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
                 const int E = group_max<G>(eh);
                 if (live) {
                     if (E >= kP7Pos) ovf = true;
-                    const int e2 = sat16(E + kP7Half);
-                    const int j1 = sat16(xJ + loop), c1 = sat16(xC + loop);
-                    xJ = j1 > e2 ? j1 : e2;
-                    xC = c1 > e2 ? c1 : e2;
-                    xN = sat16(xN + loop);
-                    // max(N + move, J + move) = max(N, J) + move (saturation
-                    // is monotone)
-                    xB = sat16((xN > xJ ? xN : xJ) + move);
+                    // J = max(J + loop, E - 32), C = max(C + loop, E - 32)
+                    JC = smax(adds(JC, loop2), adds(splat16(E), half2));
+                    NN = adds(NN, loop2);
+                    // B = max(N + move, J + move) = max(N, J) + move
+                    // (saturation is monotone): the low halves
+                    Bv = adds(smax(NN, JC), move2);
                 }
             }
             done += 16;
@@ -402,7 +404,7 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
 
         // ---- finished sequences: score, then the next record ---------------
         if (ended && gstart) {
-            a.score[id] = ovf ? (int16_t)kP7Pos : (int16_t)sat16(xC + move);
+            a.score[id] = ovf ? (int16_t)kP7Pos : (int16_t)sat16((int)JC.y + move);
             a.flag[id] = ovf ? 1 : 0;
         }
         const int claimed = take();
