@@ -425,7 +425,7 @@ hmsv_status hmsv_p7_default_plan(int32_t M, hmsv_plan *plan);
  * caller's original order.  workspace: hmsv_workspace_bytes(nseq) bytes,
  * 256-byte aligned (calls sharing it must be ordered on one stream).  plan:
  * NULL for the default (plans take 1..8 waves per block, 1..16 for
- * 64-lane groups of at most 16 registers).  Lane groups take
+ * 64-lane groups of at most 18 registers or of 20).  Lane groups take
  * the records (longest first) from a queue in the workspace as they finish
  * one; each sequence runs exactly its L rows.
  * Asynchronous on the stream; allocates nothing.  Fails with HMSV_EINVAL on

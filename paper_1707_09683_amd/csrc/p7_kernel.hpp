@@ -421,12 +421,13 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     }
 }
 
-// Blocks of up to 8 wavefronts (512 threads), or 16 for 64-lane groups of
-// at most 16 registers: their LDS image allows one block per CU, and these
-// stay within the 128 VGPRs a 1024-thread block leaves (wider plans would
-// spill their cell registers).
+// Blocks of up to 8 wavefronts (512 threads), or 16 for 64-lane groups
+// whose kernel fits the 128 VGPRs of a 1024-thread block without spilling
+// (Q <= 18 and Q = 20; the compiler spills 20-40 bytes per lane at Q = 19,
+// 21 and 22): their LDS image allows one block per CU, so 16 wavefronts per
+// block is the way to 4 per SIMD.
 template <int G, int Q>
-constexpr int kP7MaxWaves = (G == 64 && Q <= 16) ? 16 : 8;
+constexpr int kP7MaxWaves = (G == 64 && (Q <= 18 || Q == 20)) ? 16 : 8;
 
 template <int G, int Q, int THREADS>
 hipError_t launch_p7_kernel(const P7Args &a, int wpb, int blocks, hipStream_t s) {

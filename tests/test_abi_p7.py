@@ -71,7 +71,9 @@ def test_p7_score_rejects_bad_arguments_before_launch():
     for plan in (hm.make_plan(8, 6),                   # 95 < 100 nodes
                  hm.make_plan(6, 9),                   # G not a power of two
                  hm.make_plan(8, 7, waves_per_block=9),
-                 hm.make_plan(32, 2, waves_per_block=9)):
+                 hm.make_plan(32, 2, waves_per_block=9),
+                 hm.make_plan(64, 19, waves_per_block=9),   # spills as 1024 threads
+                 hm.make_plan(64, 16, waves_per_block=17)):
         assert hm._lib.hmsv_p7_score(ctypes.byref(prof), one, 1, 1, ws, ctypes.byref(plan),
                                      None) == -1, plan.as_tuple()
     unbuilt = hm.make_plan(4, 17)                      # Q beyond the G = 4 kernels
@@ -80,8 +82,12 @@ def test_p7_score_rejects_bad_arguments_before_launch():
 
 
 TUNED = {30: (8, 4), 64: (8, 4), 100: (8, 8), 200: (8, 4), 400: (16, 4), 700: (32, 8),
-         1000: (32, 8), 1100: (64, 16), 1500: (64, 16), 2047: (64, 16), 2400: (64, 8),
-         2815: (64, 8)}
+         1000: (32, 8), 1100: (64, 16), 1500: (64, 16), 2047: (64, 16), 2200: (64, 16),
+         2400: (64, 16), 2815: (64, 8)}
+
+
+def max_waves(G, Q):
+    return 16 if G == 64 and (Q <= 18 or Q == 20) else 8
 
 
 def test_p7_default_plans_cover_every_length():
@@ -89,14 +95,17 @@ def test_p7_default_plans_cover_every_length():
     for M in list(range(1, 300)) + list(range(300, 2816, 29)) + [2815]:
         p = hm.p7_default_plan(M)
         assert 2 * p.G * p.Q - 1 >= M and 64 % p.G == 0, M
-        assert p.Q == -(-(M + 1) // (2 * p.G))          # the fewest registers
+        qmin = -(-(M + 1) // (2 * p.G))
+        # the fewest registers (64 x 19 runs as 64 x 20 in 16-wavefront blocks)
+        assert p.Q == qmin or (p.G, qmin, p.Q, p.waves_per_block) == (64, 19, 20, 16), M
         assert p.Q <= (22 if p.G == 64 else 16)
+        assert 1 <= p.waves_per_block <= max_waves(p.G, p.Q)
         assert 0 < hm.p7_lds_bytes(p.G, p.Q) <= 160 * 1024
         # the nearest measured bin's plan where its group holds the profile
         b = min(TUNED, key=lambda v: (abs(math.log(v) - math.log(M)), v))
         G, wpb = TUNED[b]
         if -(-(M + 1) // (2 * G)) <= (22 if G == 64 else 16):
-            assert (p.G, p.waves_per_block) == (G, wpb), (M, b)
+            assert (p.G, p.waves_per_block) == (G, min(wpb, max_waves(p.G, p.Q))), (M, b)
     with pytest.raises(hm.HmsvError):
         hm.p7_default_plan(2816)
 

@@ -183,10 +183,10 @@ def test_p7_repeat_calls_share_workspace(hm):
     db.close()
 
 
-@pytest.mark.parametrize("Q,M", [(2, 200), (16, 2047)])
+@pytest.mark.parametrize("Q,M", [(2, 200), (16, 2047), (18, 2200), (20, 2400)])
 def test_p7_sixteen_wave_blocks(hm, Q, M):
-    """64-lane groups of at most 16 registers also run as blocks of 16
-    wavefronts (1024 threads)."""
+    """64-lane groups of at most 18 registers, or of 20, also run as blocks
+    of 16 wavefronts (1024 threads)."""
     e, t = _profile(71 + M, M)
     res, off = _db(72 + M, M, e, t, 600, 0, 900, frac=0.3)
     print(f"case p7 16-wave blocks Q={Q} M={M}", flush=True)
