@@ -210,7 +210,7 @@ def resources(jobs: int | None = None) -> str:
                      f"{plan_lds_bytes(64, qx) / 1024:.1f} |")
     # P7Viterbi: the default plans at the measured profile lengths
     from paper_1707_09683_amd import p7_default_plan, p7_lds_bytes
-    p7_bins = (30, 64, 100, 200, 400, 700, 1000, 1100, 1500, 2047, 2400, 2815)
+    p7_bins = (30, 64, 100, 200, 400, 700, 1000, 1100, 1500, 2047, 2200, 2400, 2815)
     p7_plans = {}
     for M in p7_bins:
         pl = p7_default_plan(M)
@@ -231,7 +231,8 @@ def resources(jobs: int | None = None) -> str:
             for m in rx.finditer(err):
                 k, v = m.group(1), m.group(2)
                 if k == "Function Name":
-                    cur = (G, Q) if re.search(r"p7_kernelILi\d+ELi\d+ELi\d+E", v) else None
+                    mm = re.search(r"p7_kernelILi\d+ELi\d+ELi(\d+)E", v)
+                    cur = (G, Q, int(mm.group(1))) if mm else None
                     if cur:
                         p7_use[cur] = {}
                 elif cur:
@@ -242,7 +243,7 @@ def resources(jobs: int | None = None) -> str:
               "waves/SIMD (VGPRs) | LDS KiB/block | waves/SIMD (launch) |",
               "|---|---|---|---|---|---|---|---|---|---|"]
     for (G, Q, wpb), Ms in sorted(p7_plans.items(), key=lambda t: min(t[1])):
-        u = p7_use.get((G, Q), {})
+        u = p7_use.get((G, Q, 1024 if wpb > 8 else 512), {})
         lds = p7_lds_bytes(G, Q)
         occ_v = u.get("Occupancy [waves/SIMD]", 0)
         blocks = min(160 * 1024 // lds, (4 * occ_v) // wpb) if lds else 0
