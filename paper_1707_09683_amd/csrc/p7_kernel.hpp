@@ -19,16 +19,18 @@
 // transition).  Packed saturating adds (v_pk_add_i16 clamp) and maxima
 // (v_pk_max_i16) update two cells per instruction.
 //
-// Per row: the M and I cells and a first pass of D within each element
-// (D's chain crosses into the next element unknown, taken as -inf); then
-// the chains are completed Farrar-style ("lazy F"): each element takes the
-// last D of the element before it (one DPP shift) and carries it along its
-// slots, max-ing it in, until no element's last D changes (max and a
-// saturating add of a fixed score commute, so the result is the sequential
-// chain's).  Scores come from LDS: 21 rows of match emissions by residue
-// (27 with the degenerate codes) and 7 rows of transitions, in the MSV
-// image's conflict-free layout.
-// The special states are updated once per row from the group's maximum.
+// Per row: M and I in place, registers in descending order; D within each
+// element in ascending order, its first slot taking the previous element's
+// last M (M->D); then the D->D chains across elements are completed
+// Farrar-style ("lazy F"): each element takes the last D of the element
+// before it (one DPP shift) and carries it along its slots, max-ing it in,
+// while some element's last D rises to a value that can still raise a
+// cell of the next row (max and a saturating add of a fixed score commute,
+// so every such value is the sequential chain's; values below that bound
+// change no M, no E and no score).  Scores come from LDS: 21 rows of match
+// emissions by residue (27 with the degenerate codes) and 7 rows of
+// transitions, in the MSV image's conflict-free layout.  The special
+// states, packed int16, are updated once per row from the group's maximum.
 //
 // Lane groups take records (longest first) from queues as they finish one;
 // the next record is loaded, and the one after it claimed, while the
@@ -215,7 +217,7 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     uint32_t off = a.pad_off, seq_off = a.pad_off, id = 0;
     int len = 0, done = 0;       // residues of the sequence, rows run so far
     int loop = 0, move = 0;      // length model: N/J/C loops, N/J->B and C->T
-    // special states, packed: JC = (J, C); NB's low half N; Bv's low half B
+X
     s16x2 JC = splat16(kP7Neg), NN = splat16(0), Bv = splat16(0);
     s16x2 loop2 = splat16(0), move2 = splat16(0);
     const s16x2 tbm2 = splat16(a.tbm), half2 = splat16(kP7Half);
