@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     uint32_t off = a.pad_off, seq_off = a.pad_off, id = 0;
     int len = 0, done = 0;       // residues of the sequence, rows run so far
     int loop = 0, move = 0;      // length model: N/J/C loops, N/J->B and C->T
-X
+    // special states, packed: JC = (J, C), NN = (N, N), B in Bv's low half
     s16x2 JC = splat16(kP7Neg), NN = splat16(0), Bv = splat16(0);
     s16x2 loop2 = splat16(0), move2 = splat16(0);
     const s16x2 tbm2 = splat16(a.tbm), half2 = splat16(kP7Half);
