@@ -436,6 +436,40 @@ hmsv_status hmsv_p7_score(const hmsv_p7_profile *prof, const hmsv_db *db, int16_
                           uint8_t *flags, void *workspace, const hmsv_plan *plan,
                           hipStream_t stream);
 
+/* ---- Pipeline stages on the device (Sec. 2.1) --------------------------
+ * The MSV/SSV stage passes on to P7Viterbi only the sequences whose filter
+ * score reaches a threshold (a few percent of a database).  hmsv_select
+ * finds them on the device and hmsv_p7_score_selected scores just those, so
+ * the stages chain on one stream with no host round trip.
+ *
+ * hmsv_select: score = a filter call's score array (device, nseq entries in
+ * the original order; uint8 for is_msv = 1, int8 for is_msv = 0), flags its
+ * overflow flags (an overflowed sequence always passes).  Writes to
+ * positions (device, int32, capacity nseq) the processing-order positions
+ * p (hmsv_db_order maps p to the original id) of the sequences with flag
+ * set or score >= threshold, in increasing p (so longest first), and their
+ * number to *count (device int32).  Deterministic.  workspace:
+ * hmsv_workspace_bytes(nseq) bytes, 256-byte aligned; it uses the part
+ * that P7 calls leave alone, so the same workspace may serve the P7 call
+ * that follows on the stream.  Asynchronous; allocates nothing.
+ * HMSV_EINVAL on null pointers, is_msv not 0/1 or a misaligned workspace,
+ * HMSV_EDEVICE if a launch fails. */
+hmsv_status hmsv_select(const hmsv_db *db, const void *score, const uint8_t *flags,
+                        int32_t is_msv, int32_t threshold, int32_t *positions, int32_t *count,
+                        void *workspace, hipStream_t stream);
+
+/* hmsv_p7_score restricted to the records at positions[0 .. *count)
+ * (device; processing-order positions in 0..nseq-1, each at most once, in
+ * any order, though longest first balances best: what hmsv_select writes;
+ * a count above nseq is taken as nseq, one below 0 as 0).  score and flags are written at those records'
+ * original ids only; every other entry keeps its value.  The other
+ * arguments and errors are hmsv_p7_score's (the launch grid is sized for the
+ * whole database; lane groups left without a record exit at once). */
+hmsv_status hmsv_p7_score_selected(const hmsv_p7_profile *prof, const hmsv_db *db,
+                                   const int32_t *positions, const int32_t *count,
+                                   int16_t *score, uint8_t *flags, void *workspace,
+                                   const hmsv_plan *plan, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

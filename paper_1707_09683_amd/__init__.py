@@ -11,6 +11,7 @@ ImportError: there is no fallback implementation.
 from __future__ import annotations
 
 import ctypes
+from typing import NamedTuple
 import os
 
 import numpy as np
@@ -139,6 +140,11 @@ _lib.hmsv_p7_default_plan.argtypes = [_i32, ctypes.POINTER(Plan)]
 _lib.hmsv_p7_score.restype = ctypes.c_int
 _lib.hmsv_p7_score.argtypes = [ctypes.POINTER(_CP7Profile), _P, _P, _P, _P,
                                ctypes.POINTER(Plan), _P]
+_lib.hmsv_select.restype = ctypes.c_int
+_lib.hmsv_select.argtypes = [_P, _P, _P, _i32, _i32, _P, _P, _P, _P]
+_lib.hmsv_p7_score_selected.restype = ctypes.c_int
+_lib.hmsv_p7_score_selected.argtypes = [ctypes.POINTER(_CP7Profile), _P, _P, _P, _P, _P, _P,
+                                        ctypes.POINTER(Plan), _P]
 
 EXPORTED = ("hmsv_strerror", "hmsv_tbm", "hmsv_tjb", "hmsv_quantize", "hmsv_db_create",
             "hmsv_db_destroy", "hmsv_db_nseq", "hmsv_db_residues", "hmsv_db_padded_rows",
@@ -150,7 +156,8 @@ EXPORTED = ("hmsv_strerror", "hmsv_tbm", "hmsv_tjb", "hmsv_quantize", "hmsv_db_c
             "hmsv_msv_score_noalloc", "hmsv_db_table_rows", "hmsv_db_default_plan",
             "hmsv_fasta_parse", "hmsv_alg1_pack",
             "hmsv_p7_quantize", "hmsv_p7_length_model",
-            "hmsv_p7_lds_bytes", "hmsv_p7_default_plan", "hmsv_p7_score")
+            "hmsv_p7_lds_bytes", "hmsv_p7_default_plan", "hmsv_p7_score",
+            "hmsv_select", "hmsv_p7_score_selected")
 
 
 def _check(rc: int, what: str):
@@ -498,6 +505,108 @@ def p7_score(profile: P7Profile, db: Database, score=None, flags=None, workspace
                                   flags.data_ptr(), workspace.data_ptr(), pl,
                                   ctypes.c_void_p(stream.cuda_stream)), "hmsv_p7_score")
     return score, flags
+
+
+def _device_tensor(t, dtype, n, dev, what):
+    if t.dtype != dtype or t.numel() < n or not t.is_contiguous() or t.device != dev:
+        raise ValueError(f"{what} must be a contiguous {dtype} tensor of >= {n} entries "
+                         f"on {dev}")
+
+
+def select(db: Database, score, flags, filt, threshold, positions=None, count=None,
+           workspace=None, stream=None):
+    """Survivors of a filter stage (see hmsv_select): the processing-order
+    positions of the sequences whose score reaches `threshold` or whose flag
+    is set, longest first, and their number, both left on the device."""
+    if filt not in ("msv", "ssv"):
+        raise ValueError("filt must be 'msv' or 'ssv'")
+    dev = score.device
+    n = db.nseq
+    _device_tensor(score, torch.uint8 if filt == "msv" else torch.int8, n, dev, "score")
+    _device_tensor(flags, torch.uint8, n, dev, "flags")
+    if positions is None:
+        positions = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    if count is None:
+        count = torch.empty(1, dtype=torch.int32, device=dev)
+    if workspace is None:
+        workspace = new_workspace(dev, n)
+    _device_tensor(positions, torch.int32, n, dev, "positions")
+    _device_tensor(count, torch.int32, 1, dev, "count")
+    if workspace.device != dev or workspace.numel() * workspace.element_size() \
+            < workspace_bytes(n):
+        raise ValueError("workspace too small or on another device")
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        _check(_lib.hmsv_select(db._h, score.data_ptr(), flags.data_ptr(),
+                                1 if filt == "msv" else 0, int(threshold), positions.data_ptr(),
+                                count.data_ptr(), workspace.data_ptr(),
+                                ctypes.c_void_p(stream.cuda_stream)), "hmsv_select")
+    return positions, count
+
+
+def p7_score_selected(profile: P7Profile, db: Database, positions, count, score, flags,
+                      workspace=None, plan=None, stream=None):
+    """P7Viterbi on the records at positions[0 .. count) only (see
+    hmsv_p7_score_selected): their entries of score/flags (original order)
+    are written, every other entry keeps its value."""
+    dev = profile.device
+    n = db.nseq
+    _device_tensor(positions, torch.int32, n, dev, "positions")
+    _device_tensor(count, torch.int32, 1, dev, "count")
+    _device_tensor(score, torch.int16, n, dev, "score")
+    _device_tensor(flags, torch.uint8, n, dev, "flags")
+    if workspace is None:
+        workspace = new_workspace(dev, n)
+    if workspace.device != dev or workspace.numel() * workspace.element_size() \
+            < workspace_bytes(n):
+        raise ValueError("workspace too small or on another device")
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    pl = ctypes.byref(plan) if plan is not None else None
+    with torch.cuda.device(dev):
+        _check(_lib.hmsv_p7_score_selected(ctypes.byref(profile._c), db._h,
+                                           positions.data_ptr(), count.data_ptr(),
+                                           score.data_ptr(), flags.data_ptr(),
+                                           workspace.data_ptr(), pl,
+                                           ctypes.c_void_p(stream.cuda_stream)),
+               "hmsv_p7_score_selected")
+    return score, flags
+
+
+class PipelineResult(NamedTuple):
+    filter_score: "torch.Tensor"   # uint8 (MSV) / int8 (SSV), original order
+    filter_flags: "torch.Tensor"
+    positions: "torch.Tensor"      # int32 processing-order positions of the survivors
+    count: "torch.Tensor"          # int32 [1]: how many survivors
+    p7_score: "torch.Tensor"       # int16, original order; -32768 where not run
+    p7_flags: "torch.Tensor"       # uint8; 0 where not run
+
+
+def pipeline(filt, profile: Profile, p7_profile: P7Profile, db: Database, threshold,
+             workspace=None, plan=None, p7_plan=None, stream=None) -> PipelineResult:
+    """The filter stage (MSV or SSV) over the whole database, the survivors
+    selected on the device, then P7Viterbi on those only: three calls on
+    one stream sharing one workspace, no host synchronisation."""
+    if filt not in ("msv", "ssv"):
+        raise ValueError("filt must be 'msv' or 'ssv'")
+    if p7_profile.device != profile.device:
+        raise ValueError("profiles on different devices")
+    dev = profile.device
+    n = db.nseq
+    if workspace is None:
+        workspace = new_workspace(dev, n)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    fn = msv_score if filt == "msv" else ssv_score
+    fs, ff = fn(profile, db, workspace=workspace, plan=plan, stream=stream)
+    pos, cnt = select(db, fs, ff, filt, threshold, workspace=workspace, stream=stream)
+    with torch.cuda.stream(stream):
+        ps = torch.full((n,), -32768, dtype=torch.int16, device=dev)
+        pf = torch.zeros(n, dtype=torch.uint8, device=dev)
+    p7_score_selected(p7_profile, db, pos, cnt, ps, pf, workspace=workspace, plan=p7_plan,
+                      stream=stream)
+    return PipelineResult(fs, ff, pos, cnt, ps, pf)
 
 
 def score_nats(filt, M, score, flags, lengths):

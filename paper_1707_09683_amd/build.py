@@ -104,6 +104,9 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
     exact_obj = os.path.join(OBJ, "exact.o")
     tasks.append(([HIPCC, *COMMON, "-c", os.path.join(CSRC, "exact.hip"), "-o", exact_obj],
                   exact_obj, _deps_hash(["exact"])))
+    select_obj = os.path.join(OBJ, "select.o")
+    tasks.append(([HIPCC, *COMMON, "-c", os.path.join(CSRC, "select.hip"), "-o", select_obj],
+                  select_obj, _deps_hash(["select"])))
     for G, lo, hi in kernel_units():
         obj = os.path.join(OBJ, f"kernels_g{G}_q{lo}_{hi}.o")
         defs = [f"-DHMSV_G={G}", f"-DHMSV_QLO={lo}", f"-DHMSV_QHI={hi}"]

@@ -1012,9 +1012,11 @@ hmsv_status hmsv_p7_default_plan(int32_t M, hmsv_plan *plan) {
     return HMSV_ENOKERNEL;
 }
 
-hmsv_status hmsv_p7_score(const hmsv_p7_profile *prof, const hmsv_db *db, int16_t *score,
-                          uint8_t *flags, void *workspace, const hmsv_plan *plan_in,
-                          hipStream_t stream) {
+namespace {
+
+hmsv_status p7_common(const hmsv_p7_profile *prof, const hmsv_db *db, const int32_t *sel,
+                      const int32_t *nsel, int16_t *score, uint8_t *flags, void *workspace,
+                      const hmsv_plan *plan_in, hipStream_t stream) {
     if (!prof || !db || !score || !flags || !workspace || !prof->msc || !prof->trans)
         return HMSV_EINVAL;
     if (prof->M < 1) return HMSV_EINVAL;
@@ -1073,7 +1075,42 @@ hmsv_status hmsv_p7_score(const hmsv_p7_profile *prof, const hmsv_db *db, int16_
     a.queue = (uint32_t *)((char *)workspace + kWsP7QueueOff);
     a.aux = (int32_t *)workspace;
     a.rows = db->table_rows;
+    a.sel = sel;
+    a.nsel = nsel;
     if (e->launch(a, plan.waves_per_block, blocks, stream) != hipSuccess) return HMSV_EDEVICE;
+    return HMSV_OK;
+}
+
+}  // namespace
+
+hmsv_status hmsv_p7_score(const hmsv_p7_profile *prof, const hmsv_db *db, int16_t *score,
+                          uint8_t *flags, void *workspace, const hmsv_plan *plan_in,
+                          hipStream_t stream) {
+    return p7_common(prof, db, nullptr, nullptr, score, flags, workspace, plan_in, stream);
+}
+
+hmsv_status hmsv_p7_score_selected(const hmsv_p7_profile *prof, const hmsv_db *db,
+                                   const int32_t *positions, const int32_t *count,
+                                   int16_t *score, uint8_t *flags, void *workspace,
+                                   const hmsv_plan *plan_in, hipStream_t stream) {
+    if (!positions || !count) return HMSV_EINVAL;
+    return p7_common(prof, db, positions, count, score, flags, workspace, plan_in, stream);
+}
+
+hmsv_status hmsv_select(const hmsv_db *db, const void *score, const uint8_t *flags,
+                        int32_t is_msv, int32_t threshold, int32_t *positions, int32_t *count,
+                        void *workspace, hipStream_t stream) {
+    if (!db || !score || !flags || !positions || !count || !workspace) return HMSV_EINVAL;
+    if (is_msv != 0 && is_msv != 1) return HMSV_EINVAL;
+    if (((uintptr_t)workspace & 255u) != 0) return HMSV_EINVAL;
+    if (db->nseq > (int64_t)INT32_MAX) return HMSV_EUNSUPPORTED;
+    // the per-block counts sit in the window area, which P7 calls leave alone
+    static_assert(kWsP7ImageOff + 160 * 1024 <= kWsWinOff, "selection scratch apart from P7");
+    int32_t *scratch = (int32_t *)((char *)workspace + kWsWinOff);
+    if (select_scratch_bytes(db->nseq) > ws_bytes(db->nseq) - kWsWinOff) return HMSV_EINVAL;
+    if (launch_select(db->d_seqs, db->nseq, score, flags, is_msv, threshold, positions, count,
+                      scratch, stream) != hipSuccess)
+        return HMSV_EDEVICE;
     return HMSV_OK;
 }
 

@@ -197,7 +197,17 @@ struct P7Args {
                            // prep kernel)
     int32_t rows;          // emission rows (kRows or kDegenRows); the 7
                            // transition rows follow them
+    const int32_t *sel;    // NULL: records 0..nseq-1; else the processing-order
+    const int32_t *nsel;   // positions sel[0 .. *nsel) (device), longest first
 };
+
+// Survivor selection (select.hip): positions (processing order) of the
+// records whose score reaches thr or whose flag is set, into pos[0 ..
+// *count); scratch: select_scratch_bytes(nseq) bytes of device memory.
+size_t select_scratch_bytes(int64_t nseq);
+hipError_t launch_select(const SeqRec *seqs, int64_t nseq, const void *score,
+                         const uint8_t *flags, int is_msv, int32_t thr, int32_t *pos,
+                         int32_t *count, int32_t *scratch, hipStream_t s);
 
 constexpr int kMaxP7G = 64;
 constexpr int kP7Parts = 16;                 // record queues of a P7 call

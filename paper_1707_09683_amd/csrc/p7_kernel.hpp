@@ -166,7 +166,11 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     };
     const uint32_t rT = (uint32_t)a.rows;    // first transition row
 
-    const int nseq = a.nseq;
+    // Records: the whole database (processing positions 0..nseq-1), or the
+    // positions a selection pass left in sel[0 .. *nsel) (a device count,
+    // known only here; never more than the database holds).
+    const int32_t *sel = a.sel;
+    const int nseq = sel ? min(*a.nsel, a.nseq) : a.nseq;
     // Records come from queues (counters the prep kernel zeroed), longest
     // first: a lane group claims a record as it starts one, so a group that
     // drew a long sequence draws fewer others.  Blocks are spread over up to
@@ -183,11 +187,12 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     auto issue = [&](bool want) {
         if (want && gstart) craw = atomicAdd(ctr, 1u);
     };
-    auto take = [&]() -> int {
+    auto take = [&]() -> int {    // a processing position, or -1: none left
         int k = (int)craw;
         if constexpr (G > 1) k = __shfl(k, lane - j);
         const long long r = (long long)part + (long long)nparts * (long long)k;
-        return r < (long long)nseq ? (int)r : nseq;
+        if (r >= (long long)nseq) return -1;
+        return sel ? sel[r] : (int)r;
     };
 
     s16x2 Mr[Q], Ir[Q], Dr[Q];
@@ -195,7 +200,7 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     int t = take();
     uint4 rec = make_uint4(0u, 0u, 0u, 0u), rec16 = rec;
     uint32_t lm = 0u;
-    if (t < nseq) {
+    if (t >= 0) {
         rec = *(const uint4 *)(a.seqs + t);
         rec16 = *((const uint4 *)(a.seqs + t) + 1);
         lm = a.lenmodel[t];
@@ -206,7 +211,7 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     uint4 nrec = rec, nrec16 = rec16;
     uint32_t nlm = lm;
     auto prefetch = [&]() {
-        if (tn < nseq) {
+        if (tn >= 0) {
             nrec = *(const uint4 *)(a.seqs + tn);
             nrec16 = *((const uint4 *)(a.seqs + tn) + 1);
             nlm = a.lenmodel[tn];
@@ -225,7 +230,7 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     uint4 wv = make_uint4(0u, 0u, 0u, 0u);   // this step's 16 residues
     const s16x2 neg = splat16(kP7Neg);
     auto start = [&]() {
-        active = t < nseq;
+        active = t >= 0;
         seq_off = active ? rec.x : a.pad_off;
         off = seq_off;
         id = rec.z;

@@ -81,6 +81,30 @@ def test_p7_score_rejects_bad_arguments_before_launch():
                                  None) == -5
 
 
+
+def test_pipeline_calls_reject_bad_arguments_before_launch():
+    """hmsv_select and hmsv_p7_score_selected refuse null pointers, a bad
+    filter switch and a misaligned workspace without touching the device."""
+    one = ctypes.c_void_p(1)
+    ws = ctypes.c_void_p(256)
+    sel = hm._lib.hmsv_select
+    assert sel(None, one, one, 1, 0, one, one, ws, None) == -1
+    assert sel(one, None, one, 1, 0, one, one, ws, None) == -1
+    assert sel(one, one, None, 1, 0, one, one, ws, None) == -1
+    assert sel(one, one, one, 1, 0, None, one, ws, None) == -1
+    assert sel(one, one, one, 1, 0, one, None, ws, None) == -1
+    assert sel(one, one, one, 1, 0, one, one, None, None) == -1
+    assert sel(one, one, one, 2, 0, one, one, ws, None) == -1          # is_msv not 0/1
+    assert sel(one, one, one, 0, 0, one, one, ctypes.c_void_p(8), None) == -1
+    prof = hm._CP7Profile(100, -100, 1, 1)
+    p7s = hm._lib.hmsv_p7_score_selected
+    assert p7s(ctypes.byref(prof), one, None, one, 1, 1, ws, None, None) == -1
+    assert p7s(ctypes.byref(prof), one, one, None, 1, 1, ws, None, None) == -1
+    assert p7s(ctypes.byref(prof), None, one, one, 1, 1, ws, None, None) == -1
+    prof = hm._CP7Profile(2816, -100, 1, 1)
+    assert p7s(ctypes.byref(prof), one, one, one, 1, 1, ws, None, None) == -2
+
+
 TUNED = {30: (8, 4), 64: (8, 4), 100: (8, 8), 200: (8, 4), 400: (16, 4), 700: (32, 8),
          1000: (32, 8), 1100: (64, 16), 1500: (64, 16), 2047: (64, 16), 2200: (64, 16),
          2400: (64, 16), 2815: (64, 8)}
