@@ -346,6 +346,131 @@ def p7_leg(a, hm, torch, synth, h):
     return {"workload": "p7_500k_lognormal", "per_M": out}
 
 
+def pipeline_leg(a, hm, torch, synth, h, rate=0.022, steps=5, warmup=2):
+    """The pipeline of Sec. 2.1 on the headline database: MSV over every
+    sequence, the survivors selected on the device (threshold at the score
+    that passes about 2.2% of the sequences, the paper's MSV pass rate),
+    P7Viterbi on the survivors only; three stages on one stream, one
+    workspace, no host synchronisation.  Times each stage with HIP events;
+    checks the selection against its definition and the survivors' P7
+    scores against the oracle."""
+    import oracle
+    from oracle import p7 as op7
+    M = 400
+    emis = h["emis"]
+    trans = synth.sample_transitions(np.random.default_rng(400), M)
+    dev = h["gdb"].device
+    gdb = h["gdb"]
+    n = gdb.nseq
+    prof = hm.Profile.from_emissions(emis, synth.BG, dev)
+    p7 = hm.P7Profile.from_probabilities(emis, trans, synth.BG, dev)
+    sc = h["score"].astype(np.int64)
+    thr = int(np.ceil(np.quantile(sc, 1.0 - rate)))
+    ws = hm.new_workspace(dev, n)
+    fs = torch.empty(n, dtype=torch.uint8, device=dev)
+    ff = torch.empty(n, dtype=torch.uint8, device=dev)
+    pos = torch.empty(n, dtype=torch.int32, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    ps = torch.empty(n, dtype=torch.int16, device=dev)
+    pf = torch.empty(n, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    mplan = hm.plan_for("msv", M)
+    out = {"workload": "msv_select_p7_m400_500k_lognormal", "M": M, "threshold": thr,
+           "per_plan": []}
+    # the selected call's own default (64-lane groups), then the full-database
+    # default plan and a 32-lane one
+    plans = [None, hm.p7_default_plan(M), hm.make_plan(32, 7, 8)]
+    for pplan in plans:
+        ev = []
+        for i in range(warmup + steps):
+            e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+            e0.record(stream)
+            hm.msv_score(prof, gdb, fs, ff, ws, mplan, stream)
+            e1.record(stream)
+            hm.select(gdb, fs, ff, "msv", thr, pos, cnt, ws, stream)
+            e2.record(stream)
+            hm.p7_score_selected(p7, gdb, pos, cnt, ps, pf, ws, pplan, stream)
+            e3.record(stream)
+            if i >= warmup:
+                ev.append((e0, e1, e2, e3))
+        torch.cuda.synchronize()
+        t = np.array([[x.elapsed_time(y) for x, y in ((e0, e1), (e1, e2), (e2, e3), (e0, e3))]
+                      for e0, e1, e2, e3 in ev]) * 1e-3
+        ms = np.median(t, axis=0)
+        c = int(cnt.cpu()[0])
+        sel = pos[:c].cpu().numpy()
+        order = gdb.order()
+        fsn, ffn = fs.cpu().numpy(), ff.cpu().numpy()
+        keep = np.nonzero((ffn[order] != 0) | (fsn[order].astype(np.int64) >= thr))[0]
+        sel_ok = np.array_equal(sel, keep)
+        ids = order[sel]
+        ps_o, pf_o = oracle.p7_score_db(op7.quantize(emis, trans, synth.BG), h["db"].res,
+                                        h["db"].offsets, ids=ids, nthreads=nthreads(a))
+        psn, pfn = ps.cpu().numpy(), pf.cpu().numpy()
+        bad = int(((psn[ids] != ps_o[ids]) | (pfn[ids] != pf_o[ids])).sum())
+        surv_res = int(np.asarray(h["db"].lengths)[ids].sum())
+        q64 = (M + 128) // 128
+        plan_used = (pplan.as_tuple() if pplan is not None
+                     else (64, q64, 16 if q64 <= 18 or q64 == 20 else 8, 0))
+        out["per_plan"].append({
+            "p7_plan": list(plan_used), "survivors": c, "survivor_frac": round(c / n, 5),
+            "survivor_residues": surv_res,
+            "ms": {"msv": round(ms[0] * 1e3, 4), "select": round(ms[1] * 1e3, 4),
+                   "p7": round(ms[2] * 1e3, 4), "total": round(ms[3] * 1e3, 4)},
+            "msv_gcups": round(M * h["db"].residues / ms[0] / 1e9, 1),
+            "p7_gcups_on_survivors": round(M * surv_res / ms[2] / 1e9, 1),
+            "pipeline_gcups": round(M * h["db"].residues / ms[3] / 1e9, 1),
+            "selection": "matches its definition" if sel_ok else "MISMATCH",
+            "parity": "bit-exact" if bad == 0 else f"{bad} mismatches"})
+    out["overlap"] = pipeline_overlap(hm, torch, synth, h, emis, trans, thr)
+    return out
+
+
+def pipeline_overlap(hm, torch, synth, h, emis, trans, thr, nprof=4, reps=3):
+    """Several queries through the pipeline: one stream after another, then
+    spread over two and three streams, so that one query's P7 stage (bound by its
+    longest survivors, a few waves) runs beside the next query's MSV stage.
+    Each query owns its buffers and workspace; the scores of both forms must
+    be identical."""
+    dev = h["gdb"].device
+    gdb = h["gdb"]
+    rng = np.random.default_rng(401)
+    profs = [(emis, trans)] + [(synth.sample_emissions(rng, 400),
+                                synth.sample_transitions(rng, 400)) for _ in range(nprof - 1)]
+    qs = [(hm.Profile.from_emissions(e, synth.BG, dev),
+           hm.P7Profile.from_probabilities(e, t, synth.BG, dev), hm.new_workspace(dev, gdb.nseq))
+          for e, t in profs]
+    streams = [torch.cuda.current_stream(dev), torch.cuda.Stream(dev), torch.cuda.Stream(dev)]
+
+    def run(nstreams):
+        outs = []
+        for i, (mp, pp, ws) in enumerate(qs):
+            outs.append(hm.pipeline("msv", mp, pp, gdb, thr, workspace=ws,
+                                    stream=streams[i % nstreams]))
+        return outs
+
+    res = {}
+    for ns in (1, 2, 3):
+        run(ns)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            outs = run(ns)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        res[ns] = (float(np.median(ts)), [(o.p7_score.cpu(), o.count.cpu()) for o in outs])
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+               for ns in (2, 3) for a, b in zip(res[1][1], res[ns][1]))
+    return {"queries": nprof, "M": 400, "threshold": thr,
+            "survivors": [int(c[0]) for _, c in res[1][1]],
+            "ms_one_stream": round(res[1][0] * 1e3, 3),
+            "ms_two_streams": round(res[2][0] * 1e3, 3),
+            "ms_three_streams": round(res[3][0] * 1e3, 3),
+            "wall_per_query_ms": round(min(res[2][0], res[3][0]) * 1e3 / nprof, 3),
+            "identical_one_vs_two_streams": same}
+
+
 def _median_spread(xs):
     xs = sorted(xs)
     return {"median": round(float(np.median(xs)), 4), "min": round(xs[0], 4),
@@ -551,6 +676,9 @@ def main():
         progress("p7 leg")
         extra["p7"] = p7_leg(a, hm, torch, synth, h)
         extra["layout"] = layout_leg(hm, h)
+        if a.filter == "msv" and a.M == 400:
+            progress("pipeline leg")
+            extra["pipeline"] = pipeline_leg(a, hm, torch, synth, h)
     h["gdb"].close()
     if not a.no_extra:
         progress("batched leg")
@@ -604,7 +732,10 @@ def main():
                 or ("oracle_sample" in v and "mismatch" in v["oracle_sample"])
                 or ("oracle_full" in v and "mismatch" in v["oracle_full"])
                 or any(not m.get("parity", "bit-exact").startswith("bit-exact")
-                       for m in v.get("per_M", []))]
+                       for m in v.get("per_M", []))
+                or any(m["parity"] != "bit-exact" or m["selection"] != "matches its definition"
+                       for m in v.get("per_plan", []))
+                or v.get("overlap", {}).get("identical_one_vs_two_streams") is False]
     if parity not in ("bit-exact", "not checked") or bad_legs:
         sys.exit(1)
 

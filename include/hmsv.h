@@ -464,7 +464,12 @@ hmsv_status hmsv_select(const hmsv_db *db, const void *score, const uint8_t *fla
  * a count above nseq is taken as nseq, one below 0 as 0).  score and flags are written at those records'
  * original ids only; every other entry keeps its value.  The other
  * arguments and errors are hmsv_p7_score's (the launch grid is sized for the
- * whole database; lane groups left without a record exit at once). */
+ * whole database; lane groups left without a record exit at once), except
+ * that plan = NULL picks 64-lane groups (the fewest registers per lane
+ * that hold the profile): a selection of a few percent of a database is
+ * bound by the time of its longest records, which those groups run
+ * fastest.  A selection of a large share of the database runs at higher
+ * throughput on the hmsv_p7_default_plan plan. */
 hmsv_status hmsv_p7_score_selected(const hmsv_p7_profile *prof, const hmsv_db *db,
                                    const int32_t *positions, const int32_t *count,
                                    int16_t *score, uint8_t *flags, void *workspace,

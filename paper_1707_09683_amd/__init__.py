@@ -594,16 +594,22 @@ def pipeline(filt, profile: Profile, p7_profile: P7Profile, db: Database, thresh
         raise ValueError("profiles on different devices")
     dev = profile.device
     n = db.nseq
-    if workspace is None:
-        workspace = new_workspace(dev, n)
     if stream is None:
         stream = torch.cuda.current_stream(dev)
-    fn = msv_score if filt == "msv" else ssv_score
-    fs, ff = fn(profile, db, workspace=workspace, plan=plan, stream=stream)
-    pos, cnt = select(db, fs, ff, filt, threshold, workspace=workspace, stream=stream)
+    # outputs allocated on the stream that writes them (the caching
+    # allocator reuses a block only after that stream's work on it)
     with torch.cuda.stream(stream):
+        if workspace is None:
+            workspace = new_workspace(dev, n)
+        fs = torch.empty(n, dtype=torch.uint8 if filt == "msv" else torch.int8, device=dev)
+        ff = torch.empty(n, dtype=torch.uint8, device=dev)
+        pos = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        cnt = torch.empty(1, dtype=torch.int32, device=dev)
         ps = torch.full((n,), -32768, dtype=torch.int16, device=dev)
         pf = torch.zeros(n, dtype=torch.uint8, device=dev)
+    fn = msv_score if filt == "msv" else ssv_score
+    fn(profile, db, fs, ff, workspace=workspace, plan=plan, stream=stream)
+    select(db, fs, ff, filt, threshold, pos, cnt, workspace=workspace, stream=stream)
     p7_score_selected(p7_profile, db, pos, cnt, ps, pf, workspace=workspace, plan=p7_plan,
                       stream=stream)
     return PipelineResult(fs, ff, pos, cnt, ps, pf)

@@ -1023,8 +1023,18 @@ hmsv_status p7_common(const hmsv_p7_profile *prof, const hmsv_db *db, const int3
     if (prof->M > HMSV_P7_MAX_M) return HMSV_EUNSUPPORTED;
     if (((uintptr_t)workspace & 255u) != 0) return HMSV_EINVAL;
     hmsv_plan plan;
+    const int Q64 = (prof->M + 1 + 127) / 128;
     if (plan_in) {
         plan = *plan_in;
+    } else if (sel && registry().find_p7(64, Q64) &&
+               p7_lds_bytes(64, Q64, db->table_rows) <= (size_t)kLdsBytes) {
+        // A selection holds few records, mostly started at once: the call
+        // lasts as long as its longest record, and a 64-lane group (the
+        // fewest registers per lane) runs one fastest.
+        plan.G = 64;
+        plan.Q = Q64;
+        plan.waves_per_block = p7_max_waves(64, Q64);
+        plan.blocks = 0;
     } else {
         hmsv_status st = hmsv_p7_default_plan(prof->M, &plan);
         if (st != HMSV_OK) return st;
