@@ -66,6 +66,37 @@ def test_msv_m400_500k(hm, cfg12):
     assert int(gf.sum()) >= len(w.implanted) // 2          # most implants overflow
 
 
+@pytest.mark.parametrize("M", [30, 40])
+def test_short_profiles_500k_many_segments(hm, M):
+    """Short profiles on a 500k lognormal database with 2% implants: the
+    tuned plans run one sequence per lane, so the call cuts thousands of
+    sequences into segments (as many as a call allows); every sequence of
+    both filters against the oracle."""
+    st = synth.streams(30 + M)
+    emis = synth.sample_emissions(st["profile"], M)
+    db, imp = synth.lognormal_db(30 + M, 500_000, [emis], 0.02, st)
+    gdb = hm.Database(db.res, db.offsets)
+    try:
+        for filt in ("msv", "ssv"):
+            plan = hm.plan_for(filt, M)
+            ns, nseg, T = hm.split_info(filt, M, gdb, plan)
+            print(f"case short {filt} M={M} plan={plan.as_tuple()} split={ns} segs={nseg} "
+                  f"T={T}", flush=True)
+            assert ns > 1000 and nseg > ns
+            prof = hm.Profile.from_emissions(emis, synth.BG)
+            fn = hm.msv_score if filt == "msv" else hm.ssv_score
+            s, f = fn(prof, gdb, plan=plan)
+            torch.cuda.synchronize()
+            gs, gf = s.cpu().numpy(), f.cpu().numpy()
+            es, ef = oracle.score_db(filt, oq.quantize(emis, synth.BG), db.res, db.offsets)
+            bad = np.nonzero((gs != es) | (gf != ef))[0]
+            assert bad.size == 0, (f"{filt} M={M}: {bad.size} mismatches, first {bad[:5]}: "
+                                   f"gpu {gs[bad[:5]]} oracle {es[bad[:5]]}")
+            assert (es[imp] > np.median(es)).mean() > 0.5      # the implants score high
+    finally:
+        gdb.close()
+
+
 @pytest.mark.parametrize("M", [100, 400, 1000, 2400])
 def test_ssv_500k(hm, cfg12, M):
     w, gdb = cfg12
