@@ -247,8 +247,9 @@ hmsv_status hmsv_db_default_plan(const hmsv_db *db, int32_t is_msv, int32_t M, h
  * sequences (bytes; pass the database's full sequence count, also for
  * range calls): the work-queue counters, the MSV per-residue best scores,
  * the profile converted to the kernel's LDS layout, the records of split
- * sequences' segments (at most 32768 segments of 16384 sequences per call;
- * about 2 MB), and 16 bytes per sequence for the MSV rescoring windows. */
+ * sequences' segments (at most 131072 segments of 65536 sequences per
+ * call; about 8.7 MB), and 16 bytes per sequence for the MSV rescoring
+ * windows. */
 size_t hmsv_workspace_bytes(int64_t nseq);
 
 /* ---- scoring -----------------------------------------------------------
@@ -289,7 +290,7 @@ hmsv_status hmsv_ssv_score(const hmsv_profile *prof, const hmsv_db *db,
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  As
  * hmsv_msv_score, but the workspace is the library's own device array of
- * hmsv_workspace_bytes(HMSV_NOALLOC_MAX_SEQ) bytes (about 19 MB), one per
+ * hmsv_workspace_bytes(HMSV_NOALLOC_MAX_SEQ) bytes (about 25 MB), one per
  * GPU, held until the process ends.  The call allocates nothing: no
  * hipMalloc, no host heap.  Every call on a GPU shares that GPU's array,
  * so calls that overlap on one GPU (different streams, or different host

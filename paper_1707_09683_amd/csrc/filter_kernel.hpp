@@ -254,6 +254,37 @@ constexpr int kCtrMain = 0;      // next sequence of the range
 // Flag value that marks a sequence whose score the exact pass still owes.
 constexpr uint8_t kFlagPending = 2;
 
+// MSV: "no loud step" (the offset of a lane's first loud step before it has
+// one).
+constexpr uint32_t kNoStep = 0xffffffffu;
+
+// MSV: the end of a sequence's first pass (one lane per sequence): its
+// score and flag, or, if the J state may have opened (a maximum above
+// base + tec without overflow), its rescoring window for the exact pass:
+// `warm` rows before the first loud step (not before the sequence's start)
+// to the end of the last one, never past send; the whole sequence if no
+// step was loud.  K: words of four residues per step of the filter kernel.
+template <int K>
+__device__ __forceinline__ void msv_settle(const KArgs &a, uint32_t sid, int mx,
+                                           uint32_t wfirst, uint32_t wlast, uint32_t sstart,
+                                           uint32_t send, uint32_t tjb) {
+    const bool of = mx >= 255 - a.dbias;
+    const bool loud = !of && mx > kBase + kTec;
+    if (!loud) {
+        const int v = mx - kTec;
+        a.score[sid] = of ? 255 : (uint8_t)(v < 0 ? 0 : v);
+        a.flag[sid] = of ? 1 : 0;
+        return;
+    }
+    const uint32_t w = (uint32_t)a.warm;
+    const bool known = wfirst != kNoStep && wfirst < send;
+    const uint32_t ws = known && wfirst >= sstart + w ? (wfirst - w) & ~15u : sstart;
+    uint32_t we = known ? wlast + 4u * K : send;
+    we = we < send ? we : send;
+    a.win[sid] = make_uint4(ws, (we - ws) | (tjb << 24), sid, 0u);
+    a.flag[sid] = kFlagPending;
+}
+
 // Sequence ends a wavefront collects before it leaves the row loop to
 // record scores and hand out sequences (see filter_kernel).
 template <int G>
@@ -337,7 +368,6 @@ filter_kernel(KArgs a) {
     uint32_t lvl = 0xffffffffu;  // MSV: level (two u16 halves)
     // MSV: running max over earlier steps (st.xE holds the current step's),
     // and the offsets of this lane's first and last loud steps
-    constexpr uint32_t kNoStep = 0xffffffffu;
     uint32_t xrun = 0u;
     uint32_t first_loud = kNoStep, last_loud = 0u;
     bool active = false;
@@ -565,7 +595,7 @@ filter_kernel(KArgs a) {
             // segments store theirs for combine_kernel.
             if (ended && gstart) {
                 if (id & kSegBit) {
-                    a.segx[2 * (id & ~kSegBit)] = (uint32_t)mx;
+                    a.segx[4 * (id & ~kSegBit)] = (uint32_t)mx;
                 } else {
                     bool of = mx >= 255;
                     a.score[id] = of ? (uint8_t)127 : (uint8_t)(int8_t)(mx - 128);
@@ -599,75 +629,19 @@ filter_kernel(KArgs a) {
                 ~((uint32_t)group_max<G>((int)(~first_loud ^ 0x80000000u)) ^ 0x80000000u);
             const uint32_t glast =
                 (uint32_t)group_max<G>((int)(last_loud ^ 0x80000000u)) ^ 0x80000000u;
-            bool fin = ended;            // a whole sequence ends here
-            uint32_t sid = id;           // its original index
-            uint32_t wfirst = gfirst, wlast = glast;
-            uint32_t sstart = seq_off, srt = 0u;   // its start and rows | tjb << 24
-            bool split = false;
-            // A split sequence's maximum and loud steps combine over its
-            // segments in its slot; the group that ends the last segment
-            // settles the sequence.
-            if (__any(ended && (id & kSegBit))) {
-                const bool seg = ended && (id & kSegBit);
-                uint32_t *sl = nullptr;
-                if (seg) sl = a.slots + kSlotWords * a.segx[2 * (id & ~kSegBit) + 1];
-                int last = 0;
-                if (seg && gstart) {
-                    atomicMax(sl + 1, (uint32_t)mx);
-                    if (gfirst != kNoStep) {
-                        atomicMin(sl + 4, gfirst);
-                        atomicMax(sl + 6, glast);
-                    }
-                    __threadfence();
-                    if (atomicSub(sl, 1u) == 1u) {
-                        __threadfence();
-                        last = 1;
-                    }
+            // A segment stores its maximum and loud steps for
+            // combine_msv_kernel, which settles its sequence after this
+            // kernel; a whole sequence settles here.
+            if (ended && gstart) {
+                if (id & kSegBit) {
+                    uint32_t *x = a.segx + 4 * (id & ~kSegBit);
+                    x[0] = (uint32_t)mx;
+                    x[2] = gfirst;
+                    x[3] = glast;
+                } else {
+                    msv_settle<K>(a, id, mx, gfirst, glast, seq_off, seq_end,
+                                  (uint32_t)(tjbm - a.tbm));
                 }
-                // whether the first lane ended the last segment goes to every
-                // lane of the group, which then reads the slot itself (at
-                // device scope, after the first lane's fence)
-                last = group_max<G>(last);
-                if (seg) {
-                    fin = last != 0;
-                    if (fin) {
-                        mx = (int)__hip_atomic_load(sl + 1, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-                        wfirst = __hip_atomic_load(sl + 4, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-                        wlast = __hip_atomic_load(sl + 6, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-                        sid = sl[2];
-                        split = true;
-                        const uint32_t *hr = (const uint32_t *)(recs + 2 * sl[3]);
-                        sstart = hr[0];
-                        srt = hr[1];
-                    }
-                }
-            }
-            const bool of = mx >= 255 - dbias;
-            const bool loud = fin && !of && mx > kBase + kTec;
-            if (fin && !loud && gstart) {
-                int v = mx - kTec;
-                a.score[sid] = of ? 255 : (uint8_t)(v < 0 ? 0 : v);
-                a.flag[sid] = of ? 1 : 0;
-            }
-            if (loud && gstart) {
-                // the window: `warm` rows before the first loud step (not
-                // before the sequence's start) to the end of the last one;
-                // never outside the sequence (a loud sequence always has a
-                // loud step, else the whole sequence)
-                const uint32_t w = (uint32_t)a.warm;
-                const uint32_t send =
-                    split ? sstart + (((srt & kRowsMask) + 4u * K - 1u) & ~(4u * K - 1u))
-                          : seq_end;
-                const bool known = wfirst != kNoStep && wfirst < send;
-                const uint32_t ws = known && wfirst >= sstart + w ? (wfirst - w) & ~15u : sstart;
-                uint32_t we = known ? wlast + 4u * K : send;
-                we = we < send ? we : send;
-                const uint32_t tjb = split ? srt >> 24 : (uint32_t)(tjbm - a.tbm);
-                a.win[sid] = make_uint4(ws, (we - ws) | (tjb << 24), sid, 0u);
-                a.flag[sid] = kFlagPending;
             }
             need = ended;
         }
@@ -701,7 +675,7 @@ __device__ __forceinline__ void build_segments(const KArgs &a, int t) {
         d[0] = make_uint4(off, (end - st) | (r.rt & ~kRowsMask), kSegBit | (uint32_t)(p + s),
                           w.x);
         d[1] = w;
-        a.segx[2 * (p + s) + 1] = (uint32_t)t;
+        a.segx[4 * (p + s) + 1] = (uint32_t)t;
     }
     uint4 *sl = (uint4 *)(a.slots + kSlotWords * t);
     sl[0] = make_uint4((uint32_t)bv, 0u, r.id, (uint32_t)t);
@@ -717,12 +691,36 @@ static __global__ void __launch_bounds__(256) combine_kernel(KArgs a) {
     const uint32_t v = sl[0], id = sl[2], p = sl[5];
     uint32_t m = 0;
     for (uint32_t k = 0; k < v; ++k) {
-        uint32_t x = a.segx[2 * (p + k)];
+        uint32_t x = a.segx[4 * (p + k)];
         m = x > m ? x : m;
     }
     bool of = m >= 255;
     a.score[id] = of ? (uint8_t)127 : (uint8_t)(int8_t)((int)m - 128);
     a.flag[id] = of ? 1 : 0;
+}
+
+// MSV: settle each split sequence from its segments (one thread each): the
+// maximum over them (every cell of the sequence lies in some segment's own
+// rows, and warm-up cells never exceed the true ones) and the earliest and
+// latest loud steps; then score and flag, or a rescoring window, as for a
+// whole sequence.  Runs between the filter kernel and the exact pass.
+template <int K>
+__global__ void __launch_bounds__(256) combine_msv_kernel(KArgs a) {
+    const int t = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (t >= a.nsplit) return;
+    const uint32_t *sl = a.slots + kSlotWords * t;
+    const uint32_t v = sl[0], sid = sl[2], rec = sl[3], p = sl[5];
+    int mx = 0;
+    uint32_t wfirst = kNoStep, wlast = 0u;
+    for (uint32_t k = 0; k < v; ++k) {
+        const uint4 x = *(const uint4 *)(a.segx + 4 * (p + k));
+        mx = (int)x.x > mx ? (int)x.x : mx;
+        wfirst = x.z < wfirst ? x.z : wfirst;
+        wlast = x.w > wlast ? x.w : wlast;
+    }
+    const SeqRec &r = a.seqs[rec];
+    const uint32_t send = r.off + (((r.rt & kRowsMask) + 4u * K - 1u) & ~(4u * K - 1u));
+    msv_settle<K>(a, sid, mx, wfirst, wlast, r.off, send, r.rt >> 24);
 }
 
 // One dword of a profile's LDS image for a lane group of G lanes with Q
@@ -1035,7 +1033,13 @@ hipError_t launch_filter(const KArgs &a, int wpb, int blocks, hipStream_t s) {
                        dim3(256), 0, s, a, nb, xb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if constexpr (MSV) return launch_filter_mode<G, Q, kMSV>(a, wpb, blocks, s);
+    if constexpr (MSV) {
+        e = launch_filter_mode<G, Q, kMSV>(a, wpb, blocks, s);
+        if (e != hipSuccess || a.nsplit == 0) return e;
+        hipLaunchKernelGGL(combine_msv_kernel<kWordsPerLoad<G>>, dim3((a.nsplit + 255) / 256),
+                           dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     e = launch_filter_mode<G, Q, kSSV>(a, wpb, blocks, s);
     if (e != hipSuccess || a.nsplit == 0) return e;
     hipLaunchKernelGGL(combine_kernel, dim3((a.nsplit + 255) / 256), dim3(256), 0, s, a);

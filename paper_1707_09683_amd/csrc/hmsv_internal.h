@@ -38,16 +38,15 @@ constexpr uint32_t kSegBit = 0x80000000u;     // record is a segment (ids stay b
 // seg_rows rows, each preceded by `warm` rows of the sequence (warm >= M - 1)
 // so that every cell of the segment's own rows is exact: a cell depends only
 // on the M rows above it along its diagonal.  Segment records live in the
-// workspace, with two words per segment {SSV: its maximum, its split
-// sequence}, and each split sequence has a slot of kSlotWords words:
-// {MSV: segments left, MSV: combined maximum, original id, record,
-// MSV: offset of the earliest loud step, first segment, MSV: offset of the
-// latest loud step, -} (a loud step holds a cell above the level where scB
-// would rise).  SSV segments store their maxima and a small kernel combines
-// them after the filter kernel; MSV combines in the filter kernel, whose
-// last segment decides whether the sequence needs an exact rescoring.
-constexpr int kMaxSegs = 32768;       // segment records per call
-constexpr int kMaxSplit = 16384;      // split sequences per call
+// workspace, with four words per segment {its maximum, its split sequence,
+// MSV: offset of its first loud step, MSV: offset of its last loud step}
+// (a loud step holds a cell above the level where scB would rise), and
+// each split sequence has a slot of kSlotWords words: {segments, -,
+// original id, record, -, first segment, -, -}.  The segments store their
+// results and a small kernel combines them after the filter kernel (for
+// MSV it also decides whether the sequence needs an exact rescoring).
+constexpr int kMaxSegs = 1 << 17;     // segment records per call
+constexpr int kMaxSplit = 1 << 16;    // split sequences per call
 constexpr int kMaxBins = 32;          // distinct segment counts per call
 constexpr int kSlotWords = 8;
 
@@ -71,7 +70,7 @@ struct KArgs {
     // nsegs segment records (workspace), processed first
     SeqRec *segs;          // [kMaxSegs] segment records (workspace)
     uint32_t *slots;       // [kMaxSplit][kSlotWords] per split sequence (workspace)
-    uint32_t *segx;        // [kMaxSegs][2] per segment (workspace)
+    uint32_t *segx;        // [kMaxSegs][4] per segment (workspace), 16-byte aligned
     // MSV exact pass: windows {start, rows | tjb << 24, original id, -} of
     // the sequences it rescores, by original index
     uint4 *win;            // [database nseq] (workspace)
@@ -100,7 +99,8 @@ constexpr size_t kWsCounterBytes = 256;
 constexpr size_t kWsSegOff = kWsCounterBytes + 160 * 1024;
 constexpr size_t kWsSlotOff = kWsSegOff + (size_t)kMaxSegs * sizeof(SeqRec);
 constexpr size_t kWsSegxOff = kWsSlotOff + (size_t)kMaxSplit * kSlotWords * 4;
-constexpr size_t kWsXImageOff = kWsSegxOff + (size_t)kMaxSegs * 8;
+constexpr size_t kWsXImageOff = kWsSegxOff + (size_t)kMaxSegs * 16;
+static_assert(kWsSegxOff % 16 == 0, "segment words are read as uint4");
 constexpr size_t kWsWinOff = kWsXImageOff + 160 * 1024;
 constexpr size_t ws_bytes(int64_t nseq) { return kWsWinOff + 16 * (size_t)(nseq > 1 ? nseq : 1); }
 
