@@ -257,7 +257,8 @@ size_t hmsv_workspace_bytes(int64_t nseq);
  * final scJ), flags[i] = 1 if the biased score saturated (then score = 255).
  * SSV (paper Alg. 7): score[i] = best single-segment score in signed 8-bit
  * (-128 = no positive segment), flags[i] = 1 on saturation (score = 127).
- * score, flags: device, [nseq] each, written for every sequence.
+ * score, flags: device, [nseq] each, written for every sequence (NULL
+ * allowed when the database or range holds no sequence).
  * workspace: device, hmsv_workspace_bytes(nseq) bytes, 256-byte aligned,
  * caller-owned; its content need not be initialised; calls that share a
  * workspace must be ordered on one stream.  plan: NULL for the default.  The call allocates nothing.
@@ -428,7 +429,8 @@ hmsv_status hmsv_p7_default_plan(int32_t M, hmsv_plan *plan);
  * NULL for the default (plans take 1..8 waves per block, 1..16 for
  * 64-lane groups of at most 18 registers or of 20).  Lane groups take
  * the records (longest first) from a queue in the workspace as they finish
- * one; each sequence runs exactly its L rows.
+ * one; each sequence runs exactly its L rows.  score and flags may be
+ * NULL for a database without sequences.
  * Asynchronous on the stream; allocates nothing.  Fails with HMSV_EINVAL on
  * null pointers or a bad plan, HMSV_EUNSUPPORTED for M > HMSV_P7_MAX_M,
  * HMSV_ENOKERNEL if the plan was not instantiated, HMSV_EDEVICE if the
@@ -452,7 +454,8 @@ hmsv_status hmsv_p7_score(const hmsv_p7_profile *prof, const hmsv_db *db, int16_
  * number to *count (device int32).  Deterministic.  workspace:
  * hmsv_workspace_bytes(nseq) bytes, 256-byte aligned; it uses the part
  * that P7 calls leave alone, so the same workspace may serve the P7 call
- * that follows on the stream.  Asynchronous; allocates nothing.
+ * that follows on the stream.  Asynchronous; allocates nothing.  score
+ * and flags may be NULL for a database without sequences (*count = 0).
  * HMSV_EINVAL on null pointers, is_msv not 0/1 or a misaligned workspace,
  * HMSV_EDEVICE if a launch fails. */
 hmsv_status hmsv_select(const hmsv_db *db, const void *score, const uint8_t *flags,

@@ -303,7 +303,7 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
                          const hmsv_plan *plan_in, hipStream_t stream) {
     hmsv_status st = check_profile(prof, is_msv);
     if (st != HMSV_OK) return st;
-    if (!db || !score || !flags || !workspace) return HMSV_EINVAL;
+    if (!db || !workspace) return HMSV_EINVAL;
     if (plan_in) {
         // the plan's shape first, without the database
         st = check_plan(plan_in, prof->M);
@@ -316,7 +316,8 @@ hmsv_status score_common(int is_msv, const hmsv_profile *prof, const hmsv_db *db
     if (!e) return HMSV_ENOKERNEL;
     if (count == -1 && first == 0) count = db->nseq;      // whole database
     if (first < 0 || count < 0 || first > db->nseq || count > db->nseq - first) return HMSV_EINVAL;
-    if (count == 0) return HMSV_OK;
+    if (count == 0) return HMSV_OK;          // nothing to write (outputs may be NULL)
+    if (!score || !flags) return HMSV_EINVAL;
 
     KArgs a{};
     a.cost = prof->cost;
@@ -1017,8 +1018,7 @@ namespace {
 hmsv_status p7_common(const hmsv_p7_profile *prof, const hmsv_db *db, const int32_t *sel,
                       const int32_t *nsel, int16_t *score, uint8_t *flags, void *workspace,
                       const hmsv_plan *plan_in, hipStream_t stream) {
-    if (!prof || !db || !score || !flags || !workspace || !prof->msc || !prof->trans)
-        return HMSV_EINVAL;
+    if (!prof || !db || !workspace || !prof->msc || !prof->trans) return HMSV_EINVAL;
     if (prof->M < 1) return HMSV_EINVAL;
     if (prof->M > HMSV_P7_MAX_M) return HMSV_EUNSUPPORTED;
     if (((uintptr_t)workspace & 255u) != 0) return HMSV_EINVAL;
@@ -1055,7 +1055,8 @@ hmsv_status p7_common(const hmsv_p7_profile *prof, const hmsv_db *db, const int3
     const P7KernelEntry *e = registry().find_p7(plan.G, plan.Q);
     if (!e) return HMSV_ENOKERNEL;
     if (p7_lds_bytes(plan.G, plan.Q, db->table_rows) > (size_t)kLdsBytes) return HMSV_EUNSUPPORTED;
-    if (db->nseq == 0) return HMSV_OK;
+    if (db->nseq == 0) return HMSV_OK;       // nothing to write (outputs may be NULL)
+    if (!score || !flags) return HMSV_EINVAL;
     int blocks = plan.blocks;
     if (blocks == 0) {
         int dev = 0, cus = 0;
@@ -1110,9 +1111,10 @@ hmsv_status hmsv_p7_score_selected(const hmsv_p7_profile *prof, const hmsv_db *d
 hmsv_status hmsv_select(const hmsv_db *db, const void *score, const uint8_t *flags,
                         int32_t is_msv, int32_t threshold, int32_t *positions, int32_t *count,
                         void *workspace, hipStream_t stream) {
-    if (!db || !score || !flags || !positions || !count || !workspace) return HMSV_EINVAL;
+    if (!db || !positions || !count || !workspace) return HMSV_EINVAL;
     if (is_msv != 0 && is_msv != 1) return HMSV_EINVAL;
     if (((uintptr_t)workspace & 255u) != 0) return HMSV_EINVAL;
+    if (db->nseq > 0 && (!score || !flags)) return HMSV_EINVAL;   // NULL only when empty
     if (db->nseq > (int64_t)INT32_MAX) return HMSV_EUNSUPPORTED;
     // the per-block counts sit in the window area, which P7 calls leave alone
     static_assert(kWsP7ImageOff + 160 * 1024 <= kWsWinOff, "selection scratch apart from P7");

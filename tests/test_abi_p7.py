@@ -84,13 +84,13 @@ def test_p7_score_rejects_bad_arguments_before_launch():
 
 def test_pipeline_calls_reject_bad_arguments_before_launch():
     """hmsv_select and hmsv_p7_score_selected refuse null pointers, a bad
-    filter switch and a misaligned workspace without touching the device."""
+    filter switch and a misaligned workspace without touching the device
+    (null scores and flags are refused only for a non-empty database, which
+    needs a device to build: the GPU tests cover the empty one)."""
     one = ctypes.c_void_p(1)
     ws = ctypes.c_void_p(256)
     sel = hm._lib.hmsv_select
     assert sel(None, one, one, 1, 0, one, one, ws, None) == -1
-    assert sel(one, None, one, 1, 0, one, one, ws, None) == -1
-    assert sel(one, one, None, 1, 0, one, one, ws, None) == -1
     assert sel(one, one, one, 1, 0, None, one, ws, None) == -1
     assert sel(one, one, one, 1, 0, one, None, ws, None) == -1
     assert sel(one, one, one, 1, 0, one, one, None, None) == -1

@@ -164,3 +164,44 @@ def test_p7_selected_arbitrary_subsets(hm):
             rest = np.setdiff1d(np.arange(db.nseq), took)
             assert (sn[rest] == 12345).all() and (fn_[rest] == 7).all()
     db.close()
+
+
+@pytest.mark.parametrize("filt", ["msv", "ssv"])
+def test_pipeline_edge_databases(hm, filt):
+    """An empty database, one empty sequence, one sequence, and a database
+    of empty sequences only: the survivors follow the definition (at a
+    threshold everything passes, and at one nothing but overflow passes) and
+    their P7 scores equal the oracle's."""
+    M = 40
+    rng = np.random.default_rng(990)
+    e = synth.sample_emissions(rng, M)
+    t = synth.sample_transitions(rng, M)
+    one, off1 = synth.sample_residues(rng, np.array([300], np.int64))
+    synth.implant_gapped(rng, one, off1, e, t, 1.0)
+    cases = {"no sequences": (np.zeros(0, np.uint8), np.zeros(1, np.int64)),
+             "one empty": (np.zeros(0, np.uint8), np.zeros(2, np.int64)),
+             "one": (one, off1),
+             "all empty": (np.zeros(0, np.uint8), np.zeros(101, np.int64))}
+    prof = hm.Profile.from_emissions(e, synth.BG)
+    p7 = hm.P7Profile.from_probabilities(e, t, synth.BG)
+    lo, hi = (0, 256) if filt == "msv" else (-128, 128)
+    for name, (res, off) in cases.items():
+        db = hm.Database(res, off)
+        n = db.nseq
+        fs_o, ff_o = oracle.score_db(filt, oq.quantize(e, synth.BG), res, off)
+        for thr in (lo, hi):
+            print(f"case pipeline edge {filt} {name} thr={thr}", flush=True)
+            out = hm.pipeline(filt, prof, p7, db, thr)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.filter_score.cpu().numpy(), fs_o)
+            order = db.order()
+            exp = _expected_positions(order, fs_o, ff_o, thr)
+            c = int(out.count.cpu()[0])
+            assert c == exp.size and np.array_equal(out.positions.cpu().numpy()[:c], exp)
+            ids = order[exp]
+            ps_o, pf_o = oracle.p7_score_db(op7.quantize(e, t, synth.BG), res, off, ids=ids)
+            _check_p7(out.p7_score.cpu().numpy(), out.p7_flags.cpu().numpy(), ps_o, pf_o, ids,
+                      f"{filt} {name}")
+            if thr == lo:
+                assert c == n
+        db.close()
