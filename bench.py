@@ -139,8 +139,8 @@ def calibrate_copy(mib: int):
 
 def cpu_share():
     """Host threads this process may use: the thread budget the environment
-    declares (OMP_NUM_THREADS; the GPU machine allots 16 host cores per GPU),
-    else the cores in this process's affinity mask."""
+    declares (OMP_NUM_THREADS, a host's share of cores per GPU), else the
+    cores in this process's affinity mask."""
     try:
         v = int(os.environ.get("OMP_NUM_THREADS", "0"))
     except ValueError:
