@@ -31,7 +31,7 @@ extern "C" {
 typedef int hmsv_status;
 #define HMSV_OK            0
 #define HMSV_EINVAL       -1   /* bad argument (null pointer, size, code range) */
-#define HMSV_EUNSUPPORTED -2   /* valid but beyond this build's limits */
+#define HMSV_EUNSUPPORTED -2   /* valid but beyond the library's limits */
 #define HMSV_ENOMEM       -3   /* device or host allocation failed */
 #define HMSV_EDEVICE      -4   /* a HIP runtime call failed */
 #define HMSV_ENOKERNEL    -5   /* no kernel instantiated for the requested plan */

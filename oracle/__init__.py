@@ -1,7 +1,7 @@
 """CPU oracle for the MSV and SSV filters and the gapped P7Viterbi filter.
 
 TEST INFRASTRUCTURE ONLY.  This package is the plain, slow, obviously correct
-checker that the GPU library is measured against.  Only ``tests/``,
+implementation that the GPU library's results are compared with.  Only ``tests/``,
 ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
 import it.  It shares no code with the library: its own quantizers
 (``quant.py`` for MSV/SSV, ``p7.py`` for P7Viterbi, numpy float64) and its

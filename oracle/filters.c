@@ -1,7 +1,7 @@
 /*
  * Oracle MSV and SSV filters: plain scalar C, one residue row and one model
- * node at a time.  TEST INFRASTRUCTURE ONLY: this file is the checker the
- * GPU library is compared against.  It shares no code, header or table with
+ * node at a time.  TEST INFRASTRUCTURE ONLY: the GPU library's results are
+ * compared with this file's.  It shares no code, header or table with
  * the library, and nothing in the library may call it.
  *
  * What is computed (paper Sec. 2.1 for the models, Alg. 2 and Alg. 7 for the

@@ -1,7 +1,7 @@
 /*
  * Oracle P7Viterbi filter: plain scalar C, one residue row and one model
- * node at a time.  TEST INFRASTRUCTURE ONLY: the checker the GPU library is
- * compared against; it shares no code, header or table with the library.
+ * node at a time.  TEST INFRASTRUCTURE ONLY: the GPU library's results are
+ * compared with it; it shares no code, header or table with the library.
  *
  * What is computed (paper Sec. 2.1, Eq. 1 for the match, insert and delete
  * cells; the special states N, B, E, C, J of the Plan-7 model around them),

@@ -137,7 +137,7 @@ def test_hand_worked_examples(case):
     assert oracle.ssv_seq(p2, x) == ssv_exp
 
 
-# ----------------------------------------------------- independent checkers
+# -------------------------------------------- independent implementations
 
 def unbounded_msv(r, M, bias, tbm, x):
     """MSV as an unbounded integer DP over log-odds r (no saturation anywhere).
