@@ -184,8 +184,18 @@ __global__ void __launch_bounds__(THREADS) p7_kernel(P7Args a) {
     const int part = (int)(blockIdx.x % (unsigned)nparts);
     uint32_t *ctr = a.queue + part * 32;
     uint32_t craw = 0u;
-    auto issue = [&](bool want) {
-        if (want && gstart) craw = atomicAdd(ctr, 1u);
+    auto issue = [&](bool want) {    // called by the whole wavefront
+        // one atomic per wavefront (by lane 0) for all of its claiming
+        // groups, each group's claim its rank among them
+        const bool w = want && gstart;
+        const unsigned long long m = __ballot(w);
+        if (m == 0ull) return;
+        uint32_t base = 0u;
+        if (lane == 0) base = atomicAdd(ctr, (uint32_t)__popcll(m));
+        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (w) craw = base + rank;
     };
     auto take = [&]() -> int {    // a processing position, or -1: none left
         int k = (int)craw;
