@@ -205,3 +205,33 @@ def test_pipeline_edge_databases(hm, filt):
             if thr == lo:
                 assert c == n
         db.close()
+
+
+@pytest.mark.parametrize("filt,M", [("msv", 300), ("ssv", 300), ("msv", 2000)])
+def test_pipeline_degenerate_codes(hm, filt, M):
+    """Databases holding the degenerate codes 21..26 (27-row tables in every
+    stage, and at M = 2000 the selected call's 64-lane P7 image of 34 rows):
+    survivors and their P7 scores against the oracle."""
+    e, t, res, off = _case(1000 + M, M, 1500, 0, 600, frac=0.2)
+    rng = np.random.default_rng(1001 + M)
+    deg = rng.random(res.size) < 0.03
+    res[deg] = rng.integers(21, 27, size=int(deg.sum())).astype(np.uint8)
+    fs_o, ff_o = oracle.score_db(filt, oq.quantize(e, synth.BG), res, off)
+    thr = _survivor_threshold(fs_o, 0.85)
+    db = hm.Database(res, off)
+    assert db.table_rows == 27
+    prof = hm.Profile.from_emissions(e, synth.BG)
+    p7 = hm.P7Profile.from_probabilities(e, t, synth.BG)
+    print(f"case pipeline degenerate {filt} M={M} thr={thr}", flush=True)
+    out = hm.pipeline(filt, prof, p7, db, thr)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.filter_score.cpu().numpy(), fs_o)
+    order = db.order()
+    exp = _expected_positions(order, fs_o, ff_o, thr)
+    c = int(out.count.cpu()[0])
+    assert c == exp.size and c > 0 and np.array_equal(out.positions.cpu().numpy()[:c], exp)
+    ids = order[exp]
+    ps_o, pf_o = oracle.p7_score_db(op7.quantize(e, t, synth.BG), res, off, ids=ids)
+    _check_p7(out.p7_score.cpu().numpy(), out.p7_flags.cpu().numpy(), ps_o, pf_o, ids,
+              f"degenerate {filt} M={M}")
+    db.close()
