@@ -14,7 +14,10 @@
  * 8-bit saturating arithmetic: unsigned with an offset ("dbias") for MSV
  * (Alg. 2), signed with -inf = -128 for SSV (Alg. 7).  Results are the raw
  * 8-bit filter scores and overflow flags, one per database sequence, in the
- * caller's original sequence order.
+ * caller's original sequence order.  The pipeline's next stage runs here
+ * too: the gapped P7Viterbi filter (Eq. 1, 16-bit saturating) on the whole
+ * database or, after a device-side selection of the filters' survivors,
+ * on those only (hmsv_select, hmsv_p7_score_selected).
  */
 #ifndef HMSV_H
 #define HMSV_H
