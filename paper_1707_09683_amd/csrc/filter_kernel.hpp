@@ -648,38 +648,41 @@ filter_kernel(KArgs a) {
     }
 }
 
-// Segment records and slot of split sequence t (one thread each).
-__device__ __forceinline__ void build_segments(const KArgs &a, int t) {
-    // its bin: the last with bin_t <= t (unrolled, so the kernel argument
-    // arrays are read at constant offsets)
-    int bt = 0, bp = 0, bv = 0;
+// Segment record p of the call (one thread each) and, from each split
+// sequence's first segment, the sequence's slot.
+__device__ __forceinline__ void build_segment(const KArgs &a, int p) {
+    // its bin: the last with bin_p <= p (unrolled, so the kernel argument
+    // arrays are read at constant offsets); within a bin every split
+    // sequence has bv segments, so p names sequence t and segment s
+    int bt = 0, bp = 0, bv = 1;
 #pragma unroll
     for (int b = 0; b < kMaxBins; ++b) {
-        if (b < a.nbins && a.bin_t[b] <= t) {
+        if (b < a.nbins && a.bin_p[b] <= p) {
             bt = a.bin_t[b];
             bp = a.bin_p[b];
             bv = a.bin_v[b];
         }
     }
-    const int p = bp + (t - bt) * bv;
+    const int k = (p - bp) / bv;
+    const int t = bt + k;
+    const int s = (p - bp) - k * bv;
     const SeqRec &r = a.seqs[t];
     const uint32_t rows = r.rt & kRowsMask;
     const uint32_t T = (uint32_t)a.seg_rows;
-    for (int s = 0; s < bv; ++s) {
-        uint32_t beg = (uint32_t)s * T;
-        uint32_t end = beg + T < rows ? beg + T : rows;
-        uint32_t st = s == 0 ? 0u : beg - (uint32_t)a.warm;
-        uint32_t off = r.off + st;
-        uint4 w = *(const uint4 *)(a.res + off);
-        uint4 *d = (uint4 *)(a.segs + p + s);
-        d[0] = make_uint4(off, (end - st) | (r.rt & ~kRowsMask), kSegBit | (uint32_t)(p + s),
-                          w.x);
-        d[1] = w;
-        a.segx[4 * (p + s) + 1] = (uint32_t)t;
+    const uint32_t beg = (uint32_t)s * T;
+    const uint32_t end = beg + T < rows ? beg + T : rows;
+    const uint32_t st = s == 0 ? 0u : beg - (uint32_t)a.warm;
+    const uint32_t off = r.off + st;
+    const uint4 w = *(const uint4 *)(a.res + off);
+    uint4 *d = (uint4 *)(a.segs + p);
+    d[0] = make_uint4(off, (end - st) | (r.rt & ~kRowsMask), kSegBit | (uint32_t)p, w.x);
+    d[1] = w;
+    a.segx[4 * p + 1] = (uint32_t)t;
+    if (s == 0) {
+        uint4 *sl = (uint4 *)(a.slots + kSlotWords * t);
+        sl[0] = make_uint4((uint32_t)bv, 0u, r.id, (uint32_t)t);
+        sl[1] = make_uint4(0xffffffffu, (uint32_t)p, 0u, 0u);
     }
-    uint4 *sl = (uint4 *)(a.slots + kSlotWords * t);
-    sl[0] = make_uint4((uint32_t)bv, 0u, r.id, (uint32_t)t);
-    sl[1] = make_uint4(0xffffffffu, (uint32_t)p, 0u, 0u);
 }
 
 // SSV: score and flag of each split sequence from its segments' maxima
@@ -766,8 +769,8 @@ __global__ void __launch_bounds__(256) prep_kernel(KArgs a, int image_blocks, in
     const int seg_block0 = best_block0 + (MSV ? a.rows : 0);
     const int b = (int)blockIdx.x;
     if (b >= seg_block0) {
-        int t = (b - seg_block0) * 256 + (int)threadIdx.x;
-        if (t < a.nsplit) build_segments(a, t);
+        const int p = (b - seg_block0) * 256 + (int)threadIdx.x;
+        if (p < a.nsegs) build_segment(a, p);
         return;
     }
     if (b >= best_block0) {
@@ -1028,7 +1031,7 @@ hipError_t launch_filter(const KArgs &a, int wpb, int blocks, hipStream_t s) {
     const int nb = (n + 255) / 256;
     if (wpb < 1 || wpb > kMaxWaves<G>) return hipErrorInvalidValue;
     const int xb = MSV ? (a.rows * lds_layout(kExactG, a.qx).RS + 255) / 256 : 0;
-    const int seg_blocks = (a.nsplit + 255) / 256;
+    const int seg_blocks = (a.nsegs + 255) / 256;
     hipLaunchKernelGGL((prep_kernel<G, Q, MSV>), dim3(nb + xb + (MSV ? a.rows : 0) + seg_blocks),
                        dim3(256), 0, s, a, nb, xb);
     hipError_t e = hipGetLastError();
